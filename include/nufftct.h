@@ -1,0 +1,204 @@
+/*
+ * nufftct — NUFFT projector from a 3D volume to its radially sampled
+ * first-derivative Radon space, and the exact adjoint, on one AMD MI355X (gfx950).
+ *
+ * The forward operator is module 1 of the NUFFT cone-beam forward projector
+ * (Section 2, first of its three steps; Section 2.2.1; Section 2.4.1,
+ * eq 2.16-2.18):
+ *
+ *   1. scale the volume by the deapodization factors and zero-pad it to K^3
+ *      (the diagonal P of eq 2.11),
+ *   2. unnormalised oversampled 3D FFT (F of eq 2.11),
+ *   3. J^3 Kaiser-Bessel or min-max interpolation onto the points
+ *      omega_p (T_sparse of eq 2.11; the paper's "NUFFT"),
+ *   4. optionally, per radial line, the derivative factor i*r and a 1D
+ *      inverse DFT (eq 2.17-2.18), giving derivative-Radon values.
+ *
+ * The adjoint ("NUFFT transpose", Introduction; Section 2.3) applies the
+ * conjugate transposes in reverse order: radial DFT with factor -i*r, J^3
+ * spreading, unnormalised inverse FFT, crop and deapodization.
+ *
+ * Conventions (readings where the paper is silent):
+ *   volume     x[n0][n1][n2], n2 fastest, N^3 complex values; centred index
+ *              m = n - N/2; N even.
+ *   transform  X(omega) = sum_n x[n] exp(-i omega . m), omega in rad/voxel.
+ *   points     radial plans: line l has unit direction nhat_l (3 doubles) and
+ *              N_r samples r_c = (c - N_r/2) * (2 pi / N_r), c = 0..N_r-1;
+ *              omega[l*N_r + c] = r_c * nhat_l.  Point plans take omega
+ *              directly (M x 3 doubles, row-major).
+ *   kernel     KB: psi(u) = I0(beta sqrt(1-(2u/J)^2))/I0(beta), beta <= 0
+ *              selects 2.34*J; deapodization s(m) = 1/Psi(m/K) with Psi the
+ *              kernel's continuous Fourier transform.  MINMAX_KB: per-axis
+ *              min-max coefficients c = T^-1 r with the same scaling s(m).
+ *   neighbours per axis t = omega_d / (2 pi / K) in FP64, k0 = floor(t - J/2),
+ *              taps k0+1 .. k0+J (wrapped mod K).
+ *   radial     D[l][j] = (1/N_r) sum_c f_c G[l][c] exp(+i r_c (j - N_r/2)),
+ *              f_c = i r_c (f_0 = 0) with DERIV, f_c = 1 without.
+ *   complex    interleaved (re, im); FP32 plans use complex64 (2 x float),
+ *              FP64 plans complex128 (2 x double).
+ *
+ * Memory and threads: all data pointers passed to forward/adjoint are DEVICE
+ * pointers owned by the caller, contiguous, and must not alias each other.
+ * The plan owns every table, the K^3 workspace and the point permutation.
+ * Calls are asynchronous and stream-ordered on the given stream (a
+ * hipStream_t passed as void*, NULL = the null stream); plan creation is the
+ * only blocking call.  One plan is used by one stream at a time (it holds a
+ * single workspace); separate plans are independent.  Nothing throws across
+ * this interface: every entry point returns a status code, and
+ * nufftct_last_error() returns this thread's message for the last failure.
+ * Device faults of asynchronous kernels surface at the caller's next
+ * synchronisation.
+ */
+#ifndef NUFFTCT_H
+#define NUFFTCT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nufftct_plan nufftct_plan;
+typedef struct nufftct_batch nufftct_batch;
+
+/* status codes */
+#define NUFFTCT_OK 0
+#define NUFFTCT_EINVAL 1       /* bad argument: sizes, null pointer, precision */
+#define NUFFTCT_ENOMEM 2       /* device or host allocation failed */
+#define NUFFTCT_EHIP 3         /* HIP runtime or launch error */
+#define NUFFTCT_EUNSUPPORTED 4 /* e.g. a grid size with a prime factor > 5 */
+
+/* interpolation kernels */
+#define NUFFTCT_KERNEL_KB 0
+#define NUFFTCT_KERNEL_MINMAX_KB 1
+
+/* arithmetic precision of the whole path */
+#define NUFFTCT_FP32 0 /* complex64 data; tables built in FP64 and rounded once */
+#define NUFFTCT_FP64 1 /* complex128 data, FP64 throughout */
+
+/* flags for forward / adjoint */
+#define NUFFTCT_RADIAL 1 /* apply the per-line radial (inverse) DFT stage */
+#define NUFFTCT_DERIV 2  /* with RADIAL: include the i*r derivative factor */
+#define NUFFTCT_DERIV_RADIAL 3
+
+/* stages for nufftct_stage (one stage of the path, for testing and profiling) */
+#define NUFFTCT_STAGE_PAD_FFT 0   /* vol[N^3]  -> grid[K^3] centred spectrum (F1+F2) */
+#define NUFFTCT_STAGE_INTERP 1    /* grid[K^3] -> G[M], line order (F3)             */
+#define NUFFTCT_STAGE_RADIAL 2    /* G[M]      -> D[M] (F4; flags select DERIV)       */
+#define NUFFTCT_STAGE_RADIAL_ADJ 3 /* D[M]     -> G~[M] (A4)                          */
+#define NUFFTCT_STAGE_SPREAD 4    /* G~[M]     -> grid[K^3] (A3)                     */
+#define NUFFTCT_STAGE_IFFT_CROP 5 /* grid[K^3] -> vol[N^3] (A2+A1)                   */
+
+/*
+ * Create a plan for explicit points (Section 2.1.3, eq 2.8-2.11: x~ = T x at
+ * arbitrary non-uniform points).
+ *   N          volume edge (even, >= 2)
+ *   K          oversampled grid edge (even, >= N; prime factors 2, 3, 5;
+ *              8 <= K <= 1024)
+ *   J          taps per axis, 2 <= J <= 8, J <= K
+ *   kernel     NUFFTCT_KERNEL_KB or NUFFTCT_KERNEL_MINMAX_KB
+ *   beta       KB shape; <= 0 selects 2.34*J
+ *   precision  NUFFTCT_FP32 or NUFFTCT_FP64
+ *   points     HOST pointer, M x 3 doubles (omega in rad/voxel); copied
+ *   M          number of points, 1 <= M < 2^31
+ *   n_r        0, or the radial line length when the points form lines of
+ *              n_r samples (enables NUFFTCT_RADIAL; M % n_r == 0, n_r even)
+ *   stream     stream for the plan's uploads (NULL = null stream)
+ * On success *out receives the plan; on failure *out is NULL.
+ */
+int nufftct_plan_create(nufftct_plan** out, int64_t N, int64_t K, int J, int kernel,
+                        double beta, int precision, const double* points, int64_t M,
+                        int64_t n_r, void* stream);
+
+/*
+ * Create a plan for radial lines (Section 2.1.1, eq 2.1; Section 2.2.1):
+ * n_lines unit directions (HOST pointer, n_lines x 3 doubles, copied), each
+ * line carrying n_r samples r_c = (c - n_r/2)(2 pi/n_r).  The device forms
+ * omega = r_c * nhat_l itself in FP64.  n_r even, 4 <= n_r <= 1024.  Other
+ * arguments as nufftct_plan_create.
+ */
+int nufftct_plan_create_radial(nufftct_plan** out, int64_t N, int64_t K, int J, int kernel,
+                               double beta, int precision, const double* dirs,
+                               int64_t n_lines, int64_t n_r, void* stream);
+
+/*
+ * Forward operator: vol (device, N^3 complex) -> out (device, M complex, line
+ * order p = l*n_r + c).  flags: 0 = plain NUFFT values X^(omega_p);
+ * NUFFTCT_RADIAL adds the radial inverse DFT; NUFFTCT_DERIV_RADIAL adds the
+ * derivative factor too (derivative-Radon values).
+ */
+int nufftct_forward(nufftct_plan* plan, const void* vol, void* out, int flags, void* stream);
+
+/*
+ * Adjoint (exact conjugate transpose of nufftct_forward with the same flags):
+ * in (device, M complex) -> vol (device, N^3 complex, overwritten).
+ */
+int nufftct_adjoint(nufftct_plan* plan, const void* in, void* vol, int flags, void* stream);
+
+/*
+ * Run one stage of the path (NUFFTCT_STAGE_*) from `in` to `out` (device
+ * pointers of the sizes listed with each stage).  STAGE_SPREAD overwrites all
+ * K^3 cells of `out`.  Used by the stage-parity tests and by profiling.
+ */
+int nufftct_stage(nufftct_plan* plan, int stage, const void* in, void* out, int flags,
+                  void* stream);
+
+/* Destroy a plan and free everything it owns (never the caller's buffers). */
+int nufftct_plan_destroy(nufftct_plan* plan);
+
+/* Plan introspection: sizes of the plan (any pointer may be NULL). */
+int nufftct_plan_info(const nufftct_plan* plan, int64_t* N, int64_t* K, int* J,
+                      int64_t* M, int64_t* n_r, int* precision, int64_t* workspace_bytes);
+
+/*
+ * Per-stage timing with HIP events recorded on the call's stream.
+ * nufftct_set_timing(plan, 1) starts accumulating; nufftct_get_stage_times
+ * synchronises on the recorded events and writes, for each stage s in
+ * 0..n-1 (NUFFTCT_STAGE_* order), the summed milliseconds to ms[s] and the
+ * number of timed launches to count[s] (either may be NULL), then resets.
+ */
+int nufftct_set_timing(nufftct_plan* plan, int enable);
+int nufftct_get_stage_times(nufftct_plan* plan, double* ms, int64_t* count, int n);
+
+/*
+ * Batch of independent volumes of uneven size (each with its own radial
+ * direction set), executed stage by stage so that one launch per stage
+ * covers every volume of the same grid size, with the interpolation and
+ * spreading of all volumes merged into one launch each.  The batch owns one
+ * plan per volume (created with the given parameters; J, kernel, beta and
+ * precision are shared).  Arrays are HOST arrays of length nvol; dirs[b] is
+ * a HOST pointer to n_lines[b] x 3 doubles.
+ */
+int nufftct_batch_create(nufftct_batch** out, int nvol, const int64_t* N, const int64_t* K,
+                         int J, int kernel, double beta, int precision,
+                         const double* const* dirs, const int64_t* n_lines,
+                         const int64_t* n_r, void* stream);
+
+/* vols[b], outs[b]: device pointers per volume (sizes as for that volume's plan). */
+int nufftct_batch_forward(nufftct_batch* batch, const void* const* vols, void* const* outs,
+                          int flags, void* stream);
+int nufftct_batch_adjoint(nufftct_batch* batch, const void* const* ins, void* const* vols,
+                          int flags, void* stream);
+
+/*
+ * Capture the batch's forward (dir = 0) or adjoint (dir = 1) for fixed
+ * buffers into a HIP graph owned by the batch, and replay it with
+ * nufftct_batch_graph_launch.  Replays read the same buffers given here.
+ */
+int nufftct_batch_graph_capture(nufftct_batch* batch, int dir, const void* const* src,
+                                void* const* dst, int flags, void* stream);
+int nufftct_batch_graph_launch(nufftct_batch* batch, int dir, void* stream);
+
+int nufftct_batch_destroy(nufftct_batch* batch);
+
+/* Message for this thread's most recent failure ("" if none). */
+const char* nufftct_last_error(void);
+
+/* Library version string. */
+const char* nufftct_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NUFFTCT_H */

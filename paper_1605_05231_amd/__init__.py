@@ -1,0 +1,291 @@
+"""MI355X NUFFT projector: volume -> radially sampled derivative-Radon space, and
+its exact adjoint, as hand-written HIP kernels behind a C ABI (libnufftct.so).
+
+This module only marshals arguments: every step of the projector runs in the
+library's kernels.  PyTorch supplies device memory and the current stream.
+The library must have been built (``__graft_entry__.build()``); importing
+works without it, but creating a plan raises if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import (DERIV, DERIV_RADIAL, FP32, FP64, KERNEL_KB, KERNEL_MINMAX_KB, RADIAL,  # noqa: F401
+                   STAGE_IFFT_CROP, STAGE_INTERP, STAGE_NAMES, STAGE_PAD_FFT, STAGE_RADIAL,
+                   STAGE_RADIAL_ADJ, STAGE_SPREAD, NufftError)
+
+__all__ = ["Plan", "Batch", "NufftProjector", "project", "NufftError", "version"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _check_tensor(t, n: int, dtype, name: str):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device (cuda/hip) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{name} must have {n} elements, got {t.numel()}")
+
+
+def version() -> str:
+    return _lib.load().nufftct_version().decode()
+
+
+class Plan:
+    """A NUFFT projector plan (owns tables, point binning and workspaces).
+
+    Radial plans: ``Plan(N, K, J, dirs=(L,3) float64, n_r=...)``; the points are
+    ``r_c * dirs[l]`` with ``r_c = (c - n_r/2) 2 pi / n_r``.  Point plans:
+    ``Plan(N, K, J, points=(M,3) float64[, n_r=line length])``.
+    ``dtype`` is torch.complex64 (FP32 path) or torch.complex128 (FP64 form).
+    """
+
+    def __init__(self, N: int, K: int, J: int, *, dirs=None, n_r: int = 0, points=None,
+                 kernel: str = "kb", beta: float | None = None, dtype=None, device=None):
+        torch = _torch()
+        lib = _lib.load()
+        self.dtype = dtype or torch.complex64
+        prec = {torch.complex64: FP32, torch.complex128: FP64}.get(self.dtype)
+        if prec is None:
+            raise TypeError("dtype must be torch.complex64 or torch.complex128")
+        kern = {"kb": KERNEL_KB, "minmax": KERNEL_MINMAX_KB}[kernel]
+        self.device = torch.device(device or "cuda")
+        self.N, self.K, self.J = int(N), int(K), int(J)
+        self.kernel = kernel
+        self._ptr = C.c_void_p()
+        with torch.cuda.device(self.device):
+            st = _stream_handle()
+            b = -1.0 if beta is None else float(beta)
+            if dirs is not None:
+                d = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 3))
+                self._geom = d
+                rc = lib.nufftct_plan_create_radial(
+                    C.byref(self._ptr), self.N, self.K, self.J, kern, b, prec,
+                    d.ctypes.data_as(C.POINTER(C.c_double)), d.shape[0], int(n_r), C.c_void_p(st))
+                self.n_r = int(n_r)
+                self.M = d.shape[0] * self.n_r
+            elif points is not None:
+                pts = np.ascontiguousarray(np.asarray(points, dtype=np.float64).reshape(-1, 3))
+                self._geom = pts
+                rc = lib.nufftct_plan_create(
+                    C.byref(self._ptr), self.N, self.K, self.J, kern, b, prec,
+                    pts.ctypes.data_as(C.POINTER(C.c_double)), pts.shape[0], int(n_r),
+                    C.c_void_p(st))
+                self.n_r = int(n_r)
+                self.M = pts.shape[0]
+            else:
+                raise ValueError("give dirs (radial plan) or points")
+        _lib.check(rc)
+
+    # -- lifetime ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "_ptr", None) is not None and self._ptr.value:
+            _lib.load().nufftct_plan_destroy(self._ptr)
+            self._ptr = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- sizes --------------------------------------------------------------
+    @property
+    def vol_shape(self):
+        return (self.N, self.N, self.N)
+
+    @property
+    def out_shape(self):
+        return (self.M // self.n_r, self.n_r) if self.n_r else (self.M,)
+
+    def info(self) -> dict:
+        vals = [C.c_int64(), C.c_int64(), C.c_int(), C.c_int64(), C.c_int64(), C.c_int(), C.c_int64()]
+        _lib.check(_lib.load().nufftct_plan_info(self._ptr, *[C.byref(v) for v in vals]))
+        keys = ["N", "K", "J", "M", "n_r", "precision", "workspace_bytes"]
+        return {k: v.value for k, v in zip(keys, vals)}
+
+    # -- operators ----------------------------------------------------------
+    @staticmethod
+    def _flags(radial: bool, deriv: bool) -> int:
+        return (RADIAL if radial else 0) | (DERIV if (radial and deriv) else 0)
+
+    def forward(self, x, out=None, *, radial: bool = True, deriv: bool = True, stream=None):
+        """vol (N,N,N) -> (L, n_r) derivative-Radon values (or NUFFT values)."""
+        torch = _torch()
+        radial = radial and self.n_r > 0
+        _check_tensor(x, self.N ** 3, self.dtype, "x")
+        if out is None:
+            out = torch.empty(self.out_shape, dtype=self.dtype, device=x.device)
+        _check_tensor(out, self.M, self.dtype, "out")
+        _lib.check(_lib.load().nufftct_forward(self._ptr, x.data_ptr(), out.data_ptr(),
+                                               self._flags(radial, deriv),
+                                               C.c_void_p(_stream_handle(stream))))
+        return out
+
+    def adjoint(self, y, out=None, *, radial: bool = True, deriv: bool = True, stream=None):
+        """(L, n_r) or (M,) -> vol (N,N,N): exact conjugate transpose of forward."""
+        torch = _torch()
+        radial = radial and self.n_r > 0
+        _check_tensor(y, self.M, self.dtype, "y")
+        if out is None:
+            out = torch.empty(self.vol_shape, dtype=self.dtype, device=y.device)
+        _check_tensor(out, self.N ** 3, self.dtype, "out")
+        _lib.check(_lib.load().nufftct_adjoint(self._ptr, y.data_ptr(), out.data_ptr(),
+                                               self._flags(radial, deriv),
+                                               C.c_void_p(_stream_handle(stream))))
+        return out
+
+    def stage(self, stage: int, inp, out, *, deriv: bool = True, stream=None):
+        """Run a single stage (STAGE_*); sizes: vol N^3, grid K^3, points M."""
+        sizes = {STAGE_PAD_FFT: (self.N ** 3, self.K ** 3), STAGE_INTERP: (self.K ** 3, self.M),
+                 STAGE_RADIAL: (self.M, self.M), STAGE_RADIAL_ADJ: (self.M, self.M),
+                 STAGE_SPREAD: (self.M, self.K ** 3), STAGE_IFFT_CROP: (self.K ** 3, self.N ** 3)}
+        ni, no = sizes[stage]
+        _check_tensor(inp, ni, self.dtype, "inp")
+        _check_tensor(out, no, self.dtype, "out")
+        _lib.check(_lib.load().nufftct_stage(self._ptr, stage, inp.data_ptr(), out.data_ptr(),
+                                             DERIV if deriv else 0,
+                                             C.c_void_p(_stream_handle(stream))))
+        return out
+
+    # -- timing -------------------------------------------------------------
+    def set_timing(self, on: bool = True):
+        _lib.check(_lib.load().nufftct_set_timing(self._ptr, 1 if on else 0))
+
+    def stage_times(self) -> dict:
+        ms = (C.c_double * 8)()
+        cnt = (C.c_int64 * 8)()
+        _lib.check(_lib.load().nufftct_get_stage_times(self._ptr, ms, cnt, 8))
+        return {STAGE_NAMES[i]: (ms[i], cnt[i]) for i in range(len(STAGE_NAMES))}
+
+
+class Batch:
+    """Uneven batch of radial plans sharing J, kernel and precision."""
+
+    def __init__(self, Ns, Ks, J, dirs_list, n_rs, *, kernel="kb", beta=None, dtype=None):
+        torch = _torch()
+        lib = _lib.load()
+        self.dtype = dtype or torch.complex64
+        prec = {torch.complex64: FP32, torch.complex128: FP64}[self.dtype]
+        kern = {"kb": KERNEL_KB, "minmax": KERNEL_MINMAX_KB}[kernel]
+        n = len(Ns)
+        self.Ns = [int(v) for v in Ns]
+        self.n_rs = [int(v) for v in n_rs]
+        self._dirs = [np.ascontiguousarray(np.asarray(d, dtype=np.float64).reshape(-1, 3)) for d in dirs_list]
+        self.Ms = [d.shape[0] * r for d, r in zip(self._dirs, self.n_rs)]
+        Na = (C.c_int64 * n)(*self.Ns)
+        Ka = (C.c_int64 * n)(*[int(v) for v in Ks])
+        La = (C.c_int64 * n)(*[d.shape[0] for d in self._dirs])
+        Ra = (C.c_int64 * n)(*self.n_rs)
+        Da = (C.POINTER(C.c_double) * n)(*[d.ctypes.data_as(C.POINTER(C.c_double)) for d in self._dirs])
+        self._ptr = C.c_void_p()
+        _lib.check(lib.nufftct_batch_create(C.byref(self._ptr), n, Na, Ka, int(J), kern,
+                                            -1.0 if beta is None else float(beta), prec, Da, La,
+                                            Ra, C.c_void_p(_stream_handle())))
+
+    def close(self):
+        if getattr(self, "_ptr", None) is not None and self._ptr.value:
+            _lib.load().nufftct_batch_destroy(self._ptr)
+            self._ptr = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ptrs(self, ts, sizes, name):
+        for t, n in zip(ts, sizes):
+            _check_tensor(t, n, self.dtype, name)
+        return (C.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+
+    def forward(self, xs, outs, *, deriv=True, stream=None):
+        a = self._ptrs(xs, [n ** 3 for n in self.Ns], "x")
+        b = self._ptrs(outs, self.Ms, "out")
+        _lib.check(_lib.load().nufftct_batch_forward(self._ptr, a, b, RADIAL | (DERIV if deriv else 0),
+                                                     C.c_void_p(_stream_handle(stream))))
+        return outs
+
+    def adjoint(self, ys, outs, *, deriv=True, stream=None):
+        a = self._ptrs(ys, self.Ms, "y")
+        b = self._ptrs(outs, [n ** 3 for n in self.Ns], "out")
+        _lib.check(_lib.load().nufftct_batch_adjoint(self._ptr, a, b, RADIAL | (DERIV if deriv else 0),
+                                                     C.c_void_p(_stream_handle(stream))))
+        return outs
+
+    def capture(self, direction: int, src, dst, *, deriv=True, stream=None):
+        if direction == 0:
+            a = self._ptrs(src, [n ** 3 for n in self.Ns], "x")
+            b = self._ptrs(dst, self.Ms, "out")
+        else:
+            a = self._ptrs(src, self.Ms, "y")
+            b = self._ptrs(dst, [n ** 3 for n in self.Ns], "out")
+        self._keep = (src, dst)
+        _lib.check(_lib.load().nufftct_batch_graph_capture(self._ptr, direction, a, b,
+                                                           RADIAL | (DERIV if deriv else 0),
+                                                           C.c_void_p(_stream_handle(stream))))
+
+    def replay(self, direction: int, stream=None):
+        _lib.check(_lib.load().nufftct_batch_graph_launch(self._ptr, direction,
+                                                          C.c_void_p(_stream_handle(stream))))
+
+
+def _autograd():
+    torch = _torch()
+
+    class NufftProjector(torch.autograd.Function):
+        """y = A x with A the plan's forward (derivative-Radon by default); the
+        backward applies the hand-written adjoint A^H.  Real inputs get the
+        real part of A^H g as their gradient."""
+
+        @staticmethod
+        def forward(ctx, x, plan, radial=True, deriv=True):
+            ctx.plan, ctx.radial, ctx.deriv = plan, radial, deriv
+            ctx.real_input = not x.is_complex()
+            xc = x.to(plan.dtype).contiguous()
+            return plan.forward(xc, radial=radial, deriv=deriv)
+
+        @staticmethod
+        def backward(ctx, g):
+            plan = ctx.plan
+            gx = plan.adjoint(g.to(plan.dtype).contiguous(), radial=ctx.radial, deriv=ctx.deriv)
+            if ctx.real_input:
+                gx = gx.real
+            return gx, None, None, None
+
+    return NufftProjector
+
+
+class _Lazy:
+    _cls = None
+
+    def __getattr__(self, item):
+        if _Lazy._cls is None:
+            _Lazy._cls = _autograd()
+        return getattr(_Lazy._cls, item)
+
+
+NufftProjector = _Lazy()
+
+
+def project(x, plan: Plan, radial: bool = True, deriv: bool = True):
+    """Differentiable forward projection (autograd backward = adjoint kernels)."""
+    return NufftProjector.apply(x, plan, radial, deriv)

@@ -1,0 +1,310 @@
+// Deapodize/zero-pad + oversampled 3D FFT, inverse 3D FFT + crop/deapodize,
+// and the radial derivative DFT stage, as LDS-tiled kernels for gfx950.
+//
+// Grid layout: K^3 complex, last axis fastest, stored CENTRED: cell j of an
+// axis holds frequency kappa = j - K/2.  The centring costs nothing: the
+// padded input is multiplied by (-1)^(m0+m1+m2), which shifts the spectrum of
+// an unnormalised FFT by K/2 (folded into the deapodization factor).
+//
+// Forward (F1+F2, eq 2.10-2.11 with P the deapodization):
+//   pass x : for each voxel row (n0,n1): load N values, scale by
+//            s(m0)s(m1)s(m2)(-1)^(m0+m1+m2), place at (m2 mod K), FFT along
+//            axis 2, store the K outputs at row ((m0 mod K), (m1 mod K)).
+//   pass y : for the N populated planes (m0 mod K): FFT along axis 1 loading
+//            only the N populated rows (zero-pruned), storing all K.
+//   pass z : for every (j1, j2): FFT along axis 0 loading the N populated
+//            planes, storing all K.
+// Adjoint (A2+A1) mirrors it with inverse FFTs, storing only the N needed
+// outputs of each pass and fusing the crop and deapodization into pass x.
+#pragma once
+
+#include "cx.h"
+#include "fft_lds.h"
+#include "plan.h"
+
+namespace kfft {
+
+constexpr int NT = 256;
+
+template <typename T, int L>
+constexpr int nl_line() {  // lines per tile for line-major passes
+  constexpr int target = sizeof(T) == 4 ? 4096 : 2048;
+  return target / L > 0 ? target / L : 1;
+}
+
+template <typename T, int L>
+constexpr int nl_col() {  // columns per tile for strided passes
+  if constexpr (sizeof(T) == 4) return L <= 512 ? 16 : 8;
+  return L <= 512 ? 8 : 4;
+}
+
+__device__ __forceinline__ int centred_of(int e, int K) { return e < K / 2 ? e : e - K; }
+__device__ __forceinline__ int wrap_of(int m, int K) { return m >= 0 ? m : m + K; }
+
+// ---------------------------------------------------------------------------
+// forward pass x (deapodize + pad + FFT along the contiguous axis)
+template <typename T, int L>
+__global__ __launch_bounds__(NT) void k_pad_fft_x(const cx<T>* __restrict__ vol,
+                                                  cx<T>* __restrict__ grid,
+                                                  const double* __restrict__ s,
+                                                  const cx<T>* __restrict__ tw, int N) {
+  constexpr int NL = nl_line<T, L>();
+  constexpr int K = L;
+  __shared__ cx<T> buf[fft::tile_elems<true, L, NL>()];
+  const int tid = threadIdx.x;
+  const int64_t nlines = (int64_t)N * N;
+  const int64_t line0 = (int64_t)blockIdx.x * NL;
+  const int h = N / 2;
+  for (int idx = tid; idx < NL * L; idx += NT) {
+    const int line = idx / L, e = idx % L;
+    const int64_t gl = line0 + line;
+    cx<T> v = {0, 0};
+    const int m2 = centred_of(e, K);
+    if (gl < nlines && m2 >= -h && m2 < h) {
+      const int n0 = (int)(gl / N), n1 = (int)(gl % N), n2 = m2 + h;
+      const cx<T> xv = vol[gl * N + n2];
+      double f = s[n0] * s[n1] * s[n2];
+      if ((n0 + n1 + n2 + 3 * h) & 1) f = -f;
+      v.x = (T)((double)xv.x * f);
+      v.y = (T)((double)xv.y * f);
+    }
+    buf[fft::addr<true, L, NL>(line, e)] = v;
+  }
+  __syncthreads();
+  fft::run<T, L, NL, NT, true, -1>(buf, tw, tid);
+  for (int idx = tid; idx < NL * L; idx += NT) {
+    const int line = idx / L, e = idx % L;
+    const int64_t gl = line0 + line;
+    if (gl < nlines) {
+      const int n0 = (int)(gl / N), n1 = (int)(gl % N);
+      const int q0 = wrap_of(n0 - h, K), q1 = wrap_of(n1 - h, K);
+      grid[((int64_t)q0 * K + q1) * K + e] = buf[fft::addr<true, L, NL>(line, e)];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// strided pass (axis 1 or 0): NLC adjacent columns per workgroup.
+//   outer index o: pruned -> plane (o - N/2) mod K for o < N; else o < K
+//   load_pruned : only rows whose centred index lies in [-N/2, N/2) are read
+//   store_pruned: only those rows are written
+template <typename T, int L, int S>
+__global__ __launch_bounds__(NT) void k_fft_strided(cx<T>* __restrict__ grid,
+                                                    const cx<T>* __restrict__ tw, int N,
+                                                    int64_t row_stride, int64_t outer_stride,
+                                                    int outer_pruned, int load_pruned,
+                                                    int store_pruned) {
+  constexpr int NL = nl_col<T, L>();
+  constexpr int K = L;
+  __shared__ cx<T> buf[fft::tile_elems<false, L, NL>()];
+  const int tid = threadIdx.x;
+  const int h = N / 2;
+  const int o = blockIdx.y;
+  const int qo = outer_pruned ? wrap_of(o - h, K) : o;
+  cx<T>* base = grid + (int64_t)qo * outer_stride + (int64_t)blockIdx.x * NL;
+  for (int idx = tid; idx < NL * L; idx += NT) {
+    const int line = idx % NL, e = idx / NL;
+    cx<T> v = {0, 0};
+    const int m = centred_of(e, K);
+    if (!load_pruned || (m >= -h && m < h)) v = base[e * row_stride + line];
+    buf[idx] = v;  // column-major address e*NL + line
+  }
+  __syncthreads();
+  fft::run<T, L, NL, NT, false, S>(buf, tw, tid);
+  for (int idx = tid; idx < NL * L; idx += NT) {
+    const int line = idx % NL, e = idx / NL;
+    const int m = centred_of(e, K);
+    if (!store_pruned || (m >= -h && m < h)) base[e * row_stride + line] = buf[idx];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint pass x (inverse FFT along the contiguous axis + crop + deapodize)
+template <typename T, int L>
+__global__ __launch_bounds__(NT) void k_ifft_crop_x(const cx<T>* __restrict__ grid,
+                                                    cx<T>* __restrict__ vol,
+                                                    const double* __restrict__ s,
+                                                    const cx<T>* __restrict__ tw, int N) {
+  constexpr int NL = nl_line<T, L>();
+  constexpr int K = L;
+  __shared__ cx<T> buf[fft::tile_elems<true, L, NL>()];
+  const int tid = threadIdx.x;
+  const int64_t nlines = (int64_t)N * N;
+  const int64_t line0 = (int64_t)blockIdx.x * NL;
+  const int h = N / 2;
+  for (int idx = tid; idx < NL * L; idx += NT) {
+    const int line = idx / L, e = idx % L;
+    const int64_t gl = line0 + line;
+    cx<T> v = {0, 0};
+    if (gl < nlines) {
+      const int n0 = (int)(gl / N), n1 = (int)(gl % N);
+      const int q0 = wrap_of(n0 - h, K), q1 = wrap_of(n1 - h, K);
+      v = grid[((int64_t)q0 * K + q1) * K + e];
+    }
+    buf[fft::addr<true, L, NL>(line, e)] = v;
+  }
+  __syncthreads();
+  fft::run<T, L, NL, NT, true, +1>(buf, tw, tid);
+  for (int idx = tid; idx < NL * N; idx += NT) {
+    const int line = idx / N, n2 = idx % N;
+    const int64_t gl = line0 + line;
+    if (gl < nlines) {
+      const int n0 = (int)(gl / N), n1 = (int)(gl % N);
+      const int e = wrap_of(n2 - h, K);
+      const cx<T> v = buf[fft::addr<true, L, NL>(line, e)];
+      double f = s[n0] * s[n1] * s[n2];
+      if ((n0 + n1 + n2 + 3 * h) & 1) f = -f;
+      cx<T> o;
+      o.x = (T)((double)v.x * f);
+      o.y = (T)((double)v.y * f);
+      vol[gl * N + n2] = o;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// radial stage (eq 2.17-2.18): per line of L = N_r samples
+//   forward: D_j = (1/L) sum_c f_c G_c exp(+i r_c rho_j)
+//          = (-1)^j (-1)^(L/2) / L * IDFT[(-1)^c f_c G_c]_j
+//   adjoint: G~_c = conj(f_c) (-1)^c (-1)^(L/2) / L * DFT[(-1)^j d_j]_c
+template <typename T, int L, bool ADJ>
+__global__ __launch_bounds__(NT) void k_radial(const cx<T>* __restrict__ in,
+                                               cx<T>* __restrict__ out,
+                                               const cx<T>* __restrict__ tw, int64_t nlines,
+                                               int deriv, double dr) {
+  constexpr int NL = nl_line<T, L>();
+  __shared__ cx<T> buf[fft::tile_elems<true, L, NL>()];
+  const int tid = threadIdx.x;
+  const int64_t line0 = (int64_t)blockIdx.x * NL;
+  const T post = (T)(((L / 2) & 1 ? -1.0 : 1.0) / (double)L);
+  for (int idx = tid; idx < NL * L; idx += NT) {
+    const int line = idx / L, e = idx % L;
+    const int64_t gl = line0 + line;
+    cx<T> v = {0, 0};
+    if (gl < nlines) {
+      v = in[gl * L + e];
+      if (!ADJ && deriv) {  // multiply by f_c = i r_c, f_0 = 0
+        const T r = e == 0 ? (T)0 : (T)((double)(e - L / 2) * dr);
+        v = cx<T>{-r * v.y, r * v.x};
+      }
+      if (e & 1) v = cx<T>{-v.x, -v.y};
+    }
+    buf[fft::addr<true, L, NL>(line, e)] = v;
+  }
+  __syncthreads();
+  fft::run<T, L, NL, NT, true, ADJ ? -1 : +1>(buf, tw, tid);
+  for (int idx = tid; idx < NL * L; idx += NT) {
+    const int line = idx / L, e = idx % L;
+    const int64_t gl = line0 + line;
+    if (gl < nlines) {
+      cx<T> v = buf[fft::addr<true, L, NL>(line, e)];
+      const T sc = (e & 1) ? -post : post;
+      v = cx<T>{v.x * sc, v.y * sc};
+      if (ADJ && deriv) {  // multiply by conj(f_c) = -i r_c, f_0 = 0
+        const T r = e == 0 ? (T)0 : (T)((double)(e - L / 2) * dr);
+        v = cx<T>{r * v.y, -r * v.x};
+      }
+      out[gl * L + e] = v;
+    }
+  }
+}
+
+#define KFFT_SIZES(X) \
+  X(16) X(32) X(48) X(64) X(80) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(512) X(640) X(768) X(1024)
+
+template <typename T>
+hipError_t pad_fft(const nufftct_plan& p, const void* vol, void* grid, hipStream_t st) {
+  const int N = (int)p.N, K = (int)p.K;
+  const cx<T>* tw = (const cx<T>*)p.d_tw_K;
+  cx<T>* g = (cx<T>*)grid;
+  switch (K) {
+#define CASE(LL)                                                                              \
+  case LL: {                                                                                  \
+    constexpr int NLx = nl_line<T, LL>();                                                     \
+    constexpr int NLc = nl_col<T, LL>();                                                      \
+    const int64_t nlines = (int64_t)N * N;                                                    \
+    hipLaunchKernelGGL((k_pad_fft_x<T, LL>), dim3((unsigned)((nlines + NLx - 1) / NLx)),      \
+                       dim3(NT), 0, st, (const cx<T>*)vol, g, p.d_s, tw, N);                  \
+    hipLaunchKernelGGL((k_fft_strided<T, LL, -1>), dim3(LL / NLc, N), dim3(NT), 0, st, g, tw, \
+                       N, (int64_t)LL, (int64_t)LL * LL, 1, 1, 0);                            \
+    hipLaunchKernelGGL((k_fft_strided<T, LL, -1>), dim3(LL / NLc, LL), dim3(NT), 0, st, g,    \
+                       tw, N, (int64_t)LL * LL, (int64_t)LL, 0, 1, 0);                        \
+    return hipGetLastError();                                                                 \
+  }
+    KFFT_SIZES(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t ifft_crop(const nufftct_plan& p, void* grid, void* vol, hipStream_t st) {
+  const int N = (int)p.N, K = (int)p.K;
+  const cx<T>* tw = (const cx<T>*)p.d_tw_K;
+  cx<T>* g = (cx<T>*)grid;
+  switch (K) {
+#define CASE(LL)                                                                              \
+  case LL: {                                                                                  \
+    constexpr int NLx = nl_line<T, LL>();                                                     \
+    constexpr int NLc = nl_col<T, LL>();                                                      \
+    const int64_t nlines = (int64_t)N * N;                                                    \
+    hipLaunchKernelGGL((k_fft_strided<T, LL, +1>), dim3(LL / NLc, LL), dim3(NT), 0, st, g,    \
+                       tw, N, (int64_t)LL * LL, (int64_t)LL, 0, 0, 1);                        \
+    hipLaunchKernelGGL((k_fft_strided<T, LL, +1>), dim3(LL / NLc, N), dim3(NT), 0, st, g, tw, \
+                       N, (int64_t)LL, (int64_t)LL * LL, 1, 0, 1);                            \
+    hipLaunchKernelGGL((k_ifft_crop_x<T, LL>), dim3((unsigned)((nlines + NLx - 1) / NLx)),    \
+                       dim3(NT), 0, st, (const cx<T>*)g, (cx<T>*)vol, p.d_s, tw, N);          \
+    return hipGetLastError();                                                                 \
+  }
+    KFFT_SIZES(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t radial(const nufftct_plan& p, const void* in, void* out, bool adj, bool deriv,
+                  hipStream_t st) {
+  const int64_t nl = p.M / p.n_r;
+  const cx<T>* tw = (const cx<T>*)p.d_tw_r;
+  const double dr = (2.0 * M_PI) / (double)p.n_r;
+  switch ((int)p.n_r) {
+#define CASE(LL)                                                                               \
+  case LL: {                                                                                   \
+    constexpr int NLx = nl_line<T, LL>();                                                      \
+    dim3 grd((unsigned)((nl + NLx - 1) / NLx));                                                \
+    if (adj)                                                                                   \
+      hipLaunchKernelGGL((k_radial<T, LL, true>), grd, dim3(NT), 0, st, (const cx<T>*)in,      \
+                         (cx<T>*)out, tw, nl, (int)deriv, dr);                                 \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_radial<T, LL, false>), grd, dim3(NT), 0, st, (const cx<T>*)in,     \
+                         (cx<T>*)out, tw, nl, (int)deriv, dr);                                 \
+    return hipGetLastError();                                                                  \
+  }
+    KFFT_SIZES(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace kfft
+
+#define KFFT_INSTANTIATE(T)                                                                \
+  template <>                                                                              \
+  hipError_t launch_pad_fft<T>(const nufftct_plan& p, const void* vol, void* grid,         \
+                               hipStream_t s) {                                            \
+    return kfft::pad_fft<T>(p, vol, grid, s);                                              \
+  }                                                                                        \
+  template <>                                                                              \
+  hipError_t launch_ifft_crop<T>(const nufftct_plan& p, void* grid, void* vol,             \
+                                 hipStream_t s) {                                          \
+    return kfft::ifft_crop<T>(p, grid, vol, s);                                            \
+  }                                                                                        \
+  template <>                                                                              \
+  hipError_t launch_radial<T>(const nufftct_plan& p, const void* in, void* out, bool adj,  \
+                              bool deriv, hipStream_t s) {                                 \
+    return kfft::radial<T>(p, in, out, adj, deriv, s);                                     \
+  }

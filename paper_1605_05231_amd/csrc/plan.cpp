@@ -1,0 +1,561 @@
+// C-ABI of the NUFFT derivative-Radon projector: plan construction (FP64
+// tables, point binning, workspaces), forward/adjoint orchestration, stage
+// timing and error reporting.  No exceptions cross the interface.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "plan.h"
+#include "tables.h"
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int set_last_error(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                         \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) {                                                                   \
+      int code_ = (e_ == hipErrorOutOfMemory) ? NUFFTCT_ENOMEM : NUFFTCT_EHIP;                \
+      return fail(code_, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__,     \
+                  __LINE__);                                                                  \
+    }                                                                                         \
+  } while (0)
+
+static bool is_235(int64_t L) {
+  if (L <= 0) return false;
+  while (L % 2 == 0) L /= 2;
+  while (L % 3 == 0) L /= 3;
+  while (L % 5 == 0) L /= 5;
+  return L == 1;
+}
+
+bool fft_length_supported(int64_t L) {
+  static const int64_t sizes[] = {16, 32, 48, 64, 80, 96, 128, 160,
+                                  192, 256, 320, 384, 512, 640, 768, 1024};
+  for (int64_t s : sizes)
+    if (s == L) return true;
+  return false;
+}
+
+static int env_int(const char* name, int dflt) {
+  const char* v = getenv(name);
+  if (!v || !*v) return dflt;
+  return atoi(v);
+}
+
+// ---------------------------------------------------------------------------
+// Binning: first tap per axis, bit-identical to the device rule.
+#pragma clang fp contract(off)
+static inline void host_first_taps(const double* om, int J, int64_t K, double gamma,
+                                   int (&first)[3]) {
+  for (int d = 0; d < 3; ++d) {
+    const double t = om[d] / gamma;
+    const double tj = t - 0.5 * (double)J;
+    const double k0 = std::floor(tj);
+    int64_t f = (int64_t)k0 + 1 + K / 2;
+    f %= K;
+    if (f < 0) f += K;
+    first[d] = (int)f;
+  }
+}
+
+static void point_omega(const nufftct_plan& p, const std::vector<double>& geom, int64_t i,
+                        double (&om)[3]) {
+  if (p.radial) {
+    const int64_t l = i / p.n_r;
+    const int64_t c = i - l * p.n_r;
+    const double dr = (2.0 * M_PI) / (double)p.n_r;
+    const double r = (double)(c - p.n_r / 2) * dr;
+    om[0] = r * geom[3 * l + 0];
+    om[1] = r * geom[3 * l + 1];
+    om[2] = r * geom[3 * l + 2];
+  } else {
+    om[0] = geom[3 * i + 0];
+    om[1] = geom[3 * i + 1];
+    om[2] = geom[3 * i + 2];
+  }
+}
+#pragma clang fp contract(on)
+
+static void build_bins(const nufftct_plan& p, const std::vector<double>& geom,
+                       std::vector<int32_t>& perm, std::vector<TileTask>& tasks) {
+  const int64_t M = p.M;
+  const int nb = p.nb;
+  const int64_t nbins = (int64_t)nb * nb * nb;
+  std::vector<int32_t> bin(M);
+  const double gamma = (2.0 * M_PI) / (double)p.K;
+  unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (M < 200000) nth = 1;
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < nth; ++t) {
+    th.emplace_back([&, t]() {
+      const int64_t a = M * t / nth, b = M * (t + 1) / nth;
+      for (int64_t i = a; i < b; ++i) {
+        double om[3];
+        int first[3];
+        point_omega(p, geom, i, om);
+        host_first_taps(om, p.J, p.K, gamma, first);
+        const int b0 = first[0] / p.tile, b1 = first[1] / p.tile, b2 = first[2] / p.tile;
+        bin[i] = (int32_t)(((int64_t)b0 * nb + b1) * nb + b2);
+      }
+    });
+  }
+  for (auto& t : th) t.join();
+  std::vector<int64_t> cnt(nbins + 1, 0);
+  for (int64_t i = 0; i < M; ++i) cnt[bin[i] + 1]++;
+  for (int64_t b = 0; b < nbins; ++b) cnt[b + 1] += cnt[b];
+  perm.resize(M);
+  {
+    std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+    for (int64_t i = 0; i < M; ++i) perm[pos[bin[i]]++] = (int32_t)i;
+  }
+  tasks.clear();
+  for (int64_t b = 0; b < nbins; ++b) {
+    const int64_t s = cnt[b], e = cnt[b + 1];
+    for (int64_t q = s; q < e; q += p.max_pts) {
+      TileTask t;
+      t.bin = (int32_t)b;
+      t.start = (int32_t)q;
+      t.count = (int32_t)std::min<int64_t>(p.max_pts, e - q);
+      t.pad = 0;
+      tasks.push_back(t);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+static void free_plan(nufftct_plan* p) {
+  if (!p) return;
+  hipFree(p->d_dirs);
+  hipFree(p->d_pts);
+  hipFree(p->d_s);
+  hipFree(p->d_tw_K);
+  hipFree(p->d_tw_r);
+  hipFree(p->d_perm);
+  hipFree(p->d_tasks);
+  hipFree(p->d_grid);
+  hipFree(p->d_tmp);
+  for (auto& e : p->events) {
+    hipEventDestroy(e.a);
+    hipEventDestroy(e.b);
+  }
+  delete p;
+}
+
+template <typename T>
+static int upload(void** dst, const T* src, size_t n, hipStream_t st) {
+  HIP_TRY(hipMalloc(dst, n * sizeof(T) > 0 ? n * sizeof(T) : 16));
+  if (n) HIP_TRY(hipMemcpyAsync(*dst, src, n * sizeof(T), hipMemcpyHostToDevice, st));
+  return NUFFTCT_OK;
+}
+
+static int validate(int64_t N, int64_t K, int J, int kernel, double beta, int precision,
+                    int64_t M, int64_t n_r) {
+  if (N < 2 || N % 2) return fail(NUFFTCT_EINVAL, "N must be even and >= 2 (got %lld)", (long long)N);
+  if (K < N || K % 2) return fail(NUFFTCT_EINVAL, "K must be even and >= N (got K=%lld, N=%lld)", (long long)K, (long long)N);
+  if (J < 2 || J > NUFFTCT_MAXJ || J > K)
+    return fail(NUFFTCT_EINVAL, "J must be in [2, %d] and <= K (got %d)", NUFFTCT_MAXJ, J);
+  if (kernel != NUFFTCT_KERNEL_KB && kernel != NUFFTCT_KERNEL_MINMAX_KB)
+    return fail(NUFFTCT_EINVAL, "unknown kernel %d", kernel);
+  if (precision != NUFFTCT_FP32 && precision != NUFFTCT_FP64)
+    return fail(NUFFTCT_EINVAL, "unknown precision %d", precision);
+  if (!(beta <= 3.0 * J) || std::isnan(beta))
+    return fail(NUFFTCT_EINVAL, "beta must be <= 3*J (got %g)", beta);
+  if (M < 1 || M >= (int64_t)1 << 31)
+    return fail(NUFFTCT_EINVAL, "M must be in [1, 2^31) (got %lld)", (long long)M);
+  if (n_r < 0 || (n_r > 0 && (n_r % 2 || M % n_r)))
+    return fail(NUFFTCT_EINVAL, "n_r must be 0 or an even divisor of M (got %lld)", (long long)n_r);
+  if (!is_235(K)) return fail(NUFFTCT_EUNSUPPORTED, "K=%lld has a prime factor > 5", (long long)K);
+  if (!fft_length_supported(K))
+    return fail(NUFFTCT_EUNSUPPORTED, "K=%lld is not among the compiled FFT lengths", (long long)K);
+  if (n_r > 0 && !is_235(n_r))
+    return fail(NUFFTCT_EUNSUPPORTED, "n_r=%lld has a prime factor > 5", (long long)n_r);
+  if (n_r > 0 && !fft_length_supported(n_r))
+    return fail(NUFFTCT_EUNSUPPORTED, "n_r=%lld is not among the compiled FFT lengths", (long long)n_r);
+  return NUFFTCT_OK;
+}
+
+static int create(nufftct_plan** out, int64_t N, int64_t K, int J, int kernel, double beta,
+                  int precision, int64_t M, int64_t n_r, bool radial, const double* geom,
+                  int64_t n_geom, hipStream_t st) {
+  if (!out) return fail(NUFFTCT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!geom) return fail(NUFFTCT_EINVAL, "point/direction array is NULL");
+  if (beta <= 0) beta = 2.34 * J;
+  int rc = validate(N, K, J, kernel, beta, precision, M, n_r);
+  if (rc) return rc;
+  std::vector<double> g(geom, geom + 3 * n_geom);
+  for (double v : g)
+    if (!std::isfinite(v) || std::fabs(v) > 1e6)
+      return fail(NUFFTCT_EINVAL, "points/directions must be finite and |v| <= 1e6");
+
+  nufftct_plan* p = new (std::nothrow) nufftct_plan();
+  if (!p) return fail(NUFFTCT_ENOMEM, "host allocation failed");
+  p->N = N;
+  p->K = K;
+  p->J = J;
+  p->kernel = kernel;
+  p->beta = beta;
+  p->precision = precision;
+  p->M = M;
+  p->n_r = n_r;
+  p->radial = radial;
+  p->n_lines = radial ? n_geom : (n_r ? M / n_r : 0);
+  // tile edge: the staged tile plus halo must fit in LDS and must not wrap onto itself
+  const int dflt_tile = precision == NUFFTCT_FP32 ? 16 : 8;
+  p->tile = env_int("NUFFTCT_TILE", dflt_tile);
+  if (p->tile != 8 && p->tile != 12 && p->tile != 16) p->tile = dflt_tile;
+  if (precision == NUFFTCT_FP64) p->tile = 8;
+  {
+    const int cxb = precision == NUFFTCT_FP32 ? 8 : 16;
+    auto halo_bytes = [&](int t) { return (t + J - 1) * (t + J - 1) * (t + J - 1) * cxb; };
+    while (p->tile > 8 && (p->tile + J - 1 > K || halo_bytes(p->tile) > 96 * 1024)) p->tile -= 4;
+  }
+  if (p->tile + J - 1 > K) {
+    free_plan(p);
+    return fail(NUFFTCT_EINVAL, "K=%lld too small for J=%d", (long long)K, J);
+  }
+  p->nb = (int)((K + p->tile - 1) / p->tile);
+  p->max_pts = std::max(256, env_int("NUFFTCT_MAXPTS", 4096));
+
+  auto bail = [&](int code) {
+    free_plan(p);
+    return code;
+  };
+
+  // deapodization and twiddles
+  std::vector<double> s = tables::deapod(N, K, J, beta);
+  if ((rc = upload((void**)&p->d_s, s.data(), s.size(), st))) return bail(rc);
+  if (precision == NUFFTCT_FP32) {
+    auto tk = tables::twiddles<float>(K);
+    if ((rc = upload(&p->d_tw_K, tk.data(), tk.size(), st))) return bail(rc);
+    if (n_r) {
+      auto tr = tables::twiddles<float>(n_r);
+      if ((rc = upload(&p->d_tw_r, tr.data(), tr.size(), st))) return bail(rc);
+    }
+  } else {
+    auto tk = tables::twiddles<double>(K);
+    if ((rc = upload(&p->d_tw_K, tk.data(), tk.size(), st))) return bail(rc);
+    if (n_r) {
+      auto tr = tables::twiddles<double>(n_r);
+      if ((rc = upload(&p->d_tw_r, tr.data(), tr.size(), st))) return bail(rc);
+    }
+  }
+
+  // weight polynomials
+  {
+    const int deg = precision == NUFFTCT_FP32 ? NUFFTCT_DEG_F32 : NUFFTCT_DEG_F64;
+    std::vector<long double> re, im;
+    long double err;
+    if (kernel == NUFFTCT_KERNEL_KB) {
+      err = tables::fit_kb(J, beta, deg, re);
+      im.assign(re.size(), 0.0L);
+    } else {
+      tables::MinMax mm(N, K, J, s);
+      err = tables::fit_minmax(mm, deg, re, im);
+    }
+    const long double tol = precision == NUFFTCT_FP32 ? 1e-7L : 1e-12L;
+    if (!(err <= tol)) {
+      free_plan(p);
+      return fail(NUFFTCT_EUNSUPPORTED, "weight polynomial fit error %Lg exceeds %Lg", err, tol);
+    }
+    std::memset(&p->wp32, 0, sizeof(p->wp32));
+    std::memset(&p->wp64, 0, sizeof(p->wp64));
+    for (int a = 0; a < J; ++a)
+      for (int k = 0; k <= deg; ++k) {
+        const long double r = re[(size_t)a * (deg + 1) + k], i = im[(size_t)a * (deg + 1) + k];
+        if (precision == NUFFTCT_FP32) {
+          p->wp32.re[a][k] = (float)r;
+          p->wp32.im[a][k] = (float)i;
+        } else {
+          p->wp64.re[a][k] = (double)r;
+          p->wp64.im[a][k] = (double)i;
+        }
+      }
+  }
+
+  // geometry
+  if (radial) {
+    if ((rc = upload((void**)&p->d_dirs, g.data(), g.size(), st))) return bail(rc);
+  } else {
+    if ((rc = upload((void**)&p->d_pts, g.data(), g.size(), st))) return bail(rc);
+  }
+
+  // binning
+  {
+    std::vector<int32_t> perm;
+    std::vector<TileTask> tasks;
+    build_bins(*p, g, perm, tasks);
+    p->ntasks = (int64_t)tasks.size();
+    if ((rc = upload((void**)&p->d_perm, perm.data(), perm.size(), st))) return bail(rc);
+    if ((rc = upload((void**)&p->d_tasks, tasks.data(), tasks.size(), st))) return bail(rc);
+    // host vectors go out of scope after the copies complete
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      free_plan(p);
+      return fail(NUFFTCT_EHIP, "plan upload failed: %s", hipGetErrorString(e));
+    }
+  }
+
+  // workspaces
+  const size_t cxb = precision == NUFFTCT_FP32 ? 8 : 16;
+  p->grid_bytes = (size_t)K * K * K * cxb;
+  p->tmp_bytes = (size_t)M * cxb;
+  {
+    hipError_t e = hipMalloc(&p->d_grid, p->grid_bytes);
+    if (e != hipSuccess) {
+      free_plan(p);
+      return fail(NUFFTCT_ENOMEM, "workspace of %zu bytes: %s", p->grid_bytes, hipGetErrorString(e));
+    }
+    e = hipMalloc(&p->d_tmp, p->tmp_bytes);
+    if (e != hipSuccess) {
+      free_plan(p);
+      return fail(NUFFTCT_ENOMEM, "workspace of %zu bytes: %s", p->tmp_bytes, hipGetErrorString(e));
+    }
+  }
+  *out = p;
+  g_err.clear();
+  return NUFFTCT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// stage execution with optional event timing
+struct StageTimer {
+  nufftct_plan* p;
+  hipStream_t st;
+  int stage;
+  hipEvent_t a = nullptr, b = nullptr;
+  StageTimer(nufftct_plan* p_, hipStream_t st_, int stage_) : p(p_), st(st_), stage(stage_) {
+    if (p->timing) {
+      hipEventCreate(&a);
+      hipEventCreate(&b);
+      hipEventRecord(a, st);
+    }
+  }
+  void done() {
+    if (p->timing && a) {
+      hipEventRecord(b, st);
+      p->events.push_back({a, b, stage});
+      a = b = nullptr;
+    }
+  }
+  ~StageTimer() {
+    if (a) hipEventDestroy(a);
+    if (b) hipEventDestroy(b);
+  }
+};
+
+template <typename T>
+static hipError_t run_stage(nufftct_plan* p, int stage, const void* in, void* out, int flags,
+                            hipStream_t st) {
+  StageTimer tm(p, st, stage);
+  hipError_t e = hipSuccess;
+  switch (stage) {
+    case NUFFTCT_STAGE_PAD_FFT:
+      e = launch_pad_fft<T>(*p, in, out, st);
+      break;
+    case NUFFTCT_STAGE_INTERP:
+      e = launch_interp<T>(*p, in, out, st);
+      break;
+    case NUFFTCT_STAGE_RADIAL:
+      e = launch_radial<T>(*p, in, out, false, (flags & NUFFTCT_DERIV) != 0, st);
+      break;
+    case NUFFTCT_STAGE_RADIAL_ADJ:
+      e = launch_radial<T>(*p, in, out, true, (flags & NUFFTCT_DERIV) != 0, st);
+      break;
+    case NUFFTCT_STAGE_SPREAD:
+      e = launch_zero(out, p->grid_bytes, st);
+      if (e == hipSuccess) e = launch_spread<T>(*p, in, out, st);
+      break;
+    case NUFFTCT_STAGE_IFFT_CROP:
+      // in-place on `in` (a K^3 grid the caller or the plan owns)
+      e = launch_ifft_crop<T>(*p, const_cast<void*>(in), out, st);
+      break;
+    default:
+      e = hipErrorInvalidValue;
+  }
+  tm.done();
+  return e;
+}
+
+static int check_call(nufftct_plan* p, const void* a, void* b, int flags) {
+  if (!p) return fail(NUFFTCT_EINVAL, "plan is NULL");
+  if (!a || !b) return fail(NUFFTCT_EINVAL, "data pointer is NULL");
+  if (a == b) return fail(NUFFTCT_EINVAL, "input and output must not alias");
+  if (flags & ~NUFFTCT_DERIV_RADIAL) return fail(NUFFTCT_EINVAL, "unknown flags %d", flags);
+  if ((flags & NUFFTCT_DERIV) && !(flags & NUFFTCT_RADIAL))
+    return fail(NUFFTCT_EINVAL, "NUFFTCT_DERIV requires NUFFTCT_RADIAL");
+  if ((flags & NUFFTCT_RADIAL) && p->n_r == 0)
+    return fail(NUFFTCT_EINVAL, "plan has no radial lines (n_r = 0)");
+  return NUFFTCT_OK;
+}
+
+#define STAGE_TRY(expr)                                                                     \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return fail(NUFFTCT_EHIP, "launch failed: %s", hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T>
+static int forward_impl(nufftct_plan* p, const void* vol, void* out, int flags, hipStream_t st) {
+  STAGE_TRY(run_stage<T>(p, NUFFTCT_STAGE_PAD_FFT, vol, p->d_grid, flags, st));
+  if (flags & NUFFTCT_RADIAL) {
+    STAGE_TRY(run_stage<T>(p, NUFFTCT_STAGE_INTERP, p->d_grid, p->d_tmp, flags, st));
+    STAGE_TRY(run_stage<T>(p, NUFFTCT_STAGE_RADIAL, p->d_tmp, out, flags, st));
+  } else {
+    STAGE_TRY(run_stage<T>(p, NUFFTCT_STAGE_INTERP, p->d_grid, out, flags, st));
+  }
+  return NUFFTCT_OK;
+}
+
+template <typename T>
+static int adjoint_impl(nufftct_plan* p, const void* in, void* vol, int flags, hipStream_t st) {
+  const void* src = in;
+  if (flags & NUFFTCT_RADIAL) {
+    STAGE_TRY(run_stage<T>(p, NUFFTCT_STAGE_RADIAL_ADJ, in, p->d_tmp, flags, st));
+    src = p->d_tmp;
+  }
+  STAGE_TRY(run_stage<T>(p, NUFFTCT_STAGE_SPREAD, src, p->d_grid, flags, st));
+  STAGE_TRY(run_stage<T>(p, NUFFTCT_STAGE_IFFT_CROP, p->d_grid, vol, flags, st));
+  return NUFFTCT_OK;
+}
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int nufftct_plan_create(nufftct_plan** out, int64_t N, int64_t K, int J, int kernel, double beta,
+                        int precision, const double* points, int64_t M, int64_t n_r,
+                        void* stream) {
+  return create(out, N, K, J, kernel, beta, precision, M, n_r, false, points, M,
+                (hipStream_t)stream);
+}
+
+int nufftct_plan_create_radial(nufftct_plan** out, int64_t N, int64_t K, int J, int kernel,
+                               double beta, int precision, const double* dirs, int64_t n_lines,
+                               int64_t n_r, void* stream) {
+  if (n_lines < 1) {
+    if (out) *out = nullptr;
+    return fail(NUFFTCT_EINVAL, "n_lines must be >= 1");
+  }
+  if (n_r < 4) {
+    if (out) *out = nullptr;
+    return fail(NUFFTCT_EINVAL, "n_r must be >= 4 for a radial plan");
+  }
+  if (n_lines > ((int64_t)1 << 31) / n_r) {
+    if (out) *out = nullptr;
+    return fail(NUFFTCT_EINVAL, "n_lines * n_r must be < 2^31");
+  }
+  return create(out, N, K, J, kernel, beta, precision, n_lines * n_r, n_r, true, dirs, n_lines,
+                (hipStream_t)stream);
+}
+
+int nufftct_forward(nufftct_plan* p, const void* vol, void* out, int flags, void* stream) {
+  int rc = check_call(p, vol, out, flags);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  return p->precision == NUFFTCT_FP32 ? forward_impl<float>(p, vol, out, flags, st)
+                                      : forward_impl<double>(p, vol, out, flags, st);
+}
+
+int nufftct_adjoint(nufftct_plan* p, const void* in, void* vol, int flags, void* stream) {
+  int rc = check_call(p, in, vol, flags);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  return p->precision == NUFFTCT_FP32 ? adjoint_impl<float>(p, in, vol, flags, st)
+                                      : adjoint_impl<double>(p, in, vol, flags, st);
+}
+
+int nufftct_stage(nufftct_plan* p, int stage, const void* in, void* out, int flags, void* stream) {
+  if (!p) return fail(NUFFTCT_EINVAL, "plan is NULL");
+  if (!in || !out) return fail(NUFFTCT_EINVAL, "data pointer is NULL");
+  if (in == out) return fail(NUFFTCT_EINVAL, "input and output must not alias");
+  if (stage < 0 || stage > NUFFTCT_STAGE_IFFT_CROP) return fail(NUFFTCT_EINVAL, "unknown stage %d", stage);
+  if ((stage == NUFFTCT_STAGE_RADIAL || stage == NUFFTCT_STAGE_RADIAL_ADJ) && p->n_r == 0)
+    return fail(NUFFTCT_EINVAL, "plan has no radial lines (n_r = 0)");
+  hipStream_t st = (hipStream_t)stream;
+  const void* src = in;
+  if (stage == NUFFTCT_STAGE_IFFT_CROP) {  // keep the caller's grid intact
+    HIP_TRY(hipMemcpyAsync(p->d_grid, in, p->grid_bytes, hipMemcpyDeviceToDevice, st));
+    src = p->d_grid;
+  }
+  hipError_t e = p->precision == NUFFTCT_FP32 ? run_stage<float>(p, stage, src, out, flags, st)
+                                              : run_stage<double>(p, stage, src, out, flags, st);
+  if (e != hipSuccess) return fail(NUFFTCT_EHIP, "launch failed: %s", hipGetErrorString(e));
+  return NUFFTCT_OK;
+}
+
+int nufftct_plan_destroy(nufftct_plan* p) {
+  if (!p) return NUFFTCT_OK;
+  free_plan(p);
+  return NUFFTCT_OK;
+}
+
+int nufftct_plan_info(const nufftct_plan* p, int64_t* N, int64_t* K, int* J, int64_t* M,
+                      int64_t* n_r, int* precision, int64_t* workspace_bytes) {
+  if (!p) return fail(NUFFTCT_EINVAL, "plan is NULL");
+  if (N) *N = p->N;
+  if (K) *K = p->K;
+  if (J) *J = p->J;
+  if (M) *M = p->M;
+  if (n_r) *n_r = p->n_r;
+  if (precision) *precision = p->precision;
+  if (workspace_bytes) *workspace_bytes = (int64_t)(p->grid_bytes + p->tmp_bytes);
+  return NUFFTCT_OK;
+}
+
+int nufftct_set_timing(nufftct_plan* p, int enable) {
+  if (!p) return fail(NUFFTCT_EINVAL, "plan is NULL");
+  p->timing = enable != 0;
+  return NUFFTCT_OK;
+}
+
+int nufftct_get_stage_times(nufftct_plan* p, double* ms, int64_t* count, int n) {
+  if (!p) return fail(NUFFTCT_EINVAL, "plan is NULL");
+  for (auto& e : p->events) {
+    HIP_TRY(hipEventSynchronize(e.b));
+    float t = 0;
+    HIP_TRY(hipEventElapsedTime(&t, e.a, e.b));
+    p->stage_ms[e.stage] += t;
+    p->stage_cnt[e.stage] += 1;
+    hipEventDestroy(e.a);
+    hipEventDestroy(e.b);
+  }
+  p->events.clear();
+  for (int s = 0; s < n && s < 8; ++s) {
+    if (ms) ms[s] = p->stage_ms[s];
+    if (count) count[s] = p->stage_cnt[s];
+  }
+  for (int s = 0; s < 8; ++s) {
+    p->stage_ms[s] = 0;
+    p->stage_cnt[s] = 0;
+  }
+  return NUFFTCT_OK;
+}
+
+const char* nufftct_last_error(void) { return g_err.c_str(); }
+
+const char* nufftct_version(void) { return "nufftct 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,108 @@
+// Internal plan structure and the launchers each kernel file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/nufftct.h"
+
+// Degree of the per-tap weight polynomials (piecewise Horner form of the
+// interpolation kernel on each unit interval), per precision.
+#define NUFFTCT_DEG_F32 11
+#define NUFFTCT_DEG_F64 17
+#define NUFFTCT_MAXJ 8
+
+// Per-tap polynomial coefficients of the weights in z = 2*frac - 1, where
+// frac = (t - J/2) - floor(t - J/2).  Real part only for KB; complex for min-max.
+template <typename T, int DEG>
+struct WeightPoly {
+  T re[NUFFTCT_MAXJ][DEG + 1];
+  T im[NUFFTCT_MAXJ][DEG + 1];
+};
+
+// Geometry of the non-uniform points, read by the interpolation/spreading kernels.
+struct PointGeom {
+  const double* dirs;  // radial plans: n_lines x 3 unit directions
+  const double* pts;   // point plans: M x 3 omega values
+  double dr;           // 2 pi / n_r (radial plans)
+  double gamma;        // 2 pi / K
+  int n_r;             // radial line length; 0 for point plans
+  int K;
+};
+
+struct TileTask {
+  int32_t bin;    // linear tile index (b0 * nb + b1) * nb + b2
+  int32_t start;  // first entry in the permutation
+  int32_t count;  // number of points
+  int32_t pad;
+};
+
+struct nufftct_plan {
+  int64_t N = 0, K = 0, M = 0, n_r = 0, n_lines = 0;
+  int J = 0, kernel = 0, precision = 0;
+  double beta = 0;
+  bool radial = false;
+
+  // tiling of the grid for interpolation / spreading
+  int tile = 16;      // tile edge in grid cells
+  int nb = 0;         // tiles per axis
+  int max_pts = 4096; // points per task
+
+  // device memory owned by the plan
+  double* d_dirs = nullptr;
+  double* d_pts = nullptr;
+  double* d_s = nullptr;        // deapodization s(m), N doubles
+  void* d_tw_K = nullptr;       // twiddles for length K (plan precision)
+  void* d_tw_r = nullptr;       // twiddles for length n_r
+  int32_t* d_perm = nullptr;    // M point ids sorted by tile
+  TileTask* d_tasks = nullptr;
+  int64_t ntasks = 0;
+  void* d_grid = nullptr;       // K^3 complex workspace
+  void* d_tmp = nullptr;        // M complex workspace
+  size_t grid_bytes = 0, tmp_bytes = 0;
+
+  // weight polynomials (host copies passed by value to kernels)
+  WeightPoly<float, NUFFTCT_DEG_F32> wp32;
+  WeightPoly<double, NUFFTCT_DEG_F64> wp64;
+
+  // timing
+  bool timing = false;
+  struct Ev { hipEvent_t a, b; int stage; };
+  std::vector<Ev> events;
+  double stage_ms[8] = {0};
+  int64_t stage_cnt[8] = {0};
+
+  PointGeom geom() const {
+    PointGeom g;
+    g.dirs = d_dirs;
+    g.pts = d_pts;
+    g.dr = n_r ? (2.0 * M_PI) / (double)n_r : 0.0;
+    g.gamma = (2.0 * M_PI) / (double)K;
+    g.n_r = radial ? (int)n_r : 0;
+    g.K = (int)K;
+    return g;
+  }
+};
+
+// ---- launchers (return hipSuccess or the launch error) ----
+// FFT stages (k_fft_*.hip), templated on the real type
+template <typename T>
+hipError_t launch_pad_fft(const nufftct_plan& p, const void* vol, void* grid, hipStream_t s);
+template <typename T>
+hipError_t launch_ifft_crop(const nufftct_plan& p, void* grid, void* vol, hipStream_t s);
+template <typename T>
+hipError_t launch_radial(const nufftct_plan& p, const void* in, void* out, bool adjoint,
+                         bool deriv, hipStream_t s);
+// interpolation / spreading (k_grid.hip)
+template <typename T>
+hipError_t launch_interp(const nufftct_plan& p, const void* grid, void* out, hipStream_t s);
+template <typename T>
+hipError_t launch_spread(const nufftct_plan& p, const void* in, void* grid, hipStream_t s);
+hipError_t launch_zero(void* ptr, size_t bytes, hipStream_t s);
+
+bool fft_length_supported(int64_t L);
+// record this thread's error message (read back by nufftct_last_error); returns code
+int set_last_error(int code, const std::string& msg);
