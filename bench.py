@@ -1,0 +1,259 @@
+#!/usr/bin/env python3
+"""Benchmark of the NUFFT derivative-Radon projector, forward + adjoint, on one GPU.
+
+Workload (default): a 256^3 volume of 40 random ellipsoids plus Gaussian noise
+(sigma 0.01), oversampled grid K = 512^3, J = 6 Kaiser-Bessel taps, radial
+lines at 360 azimuths x 180 polar angles with 512 samples each
+(M = 33,177,600 points), derivative + radial inverse DFT on.  One step = one
+forward (volume -> derivative-Radon values) followed by one adjoint of that
+output (-> volume), inputs resident in device memory.  Metric: Mpoints/s =
+M / (time of one step).
+
+Also reported (outside the timed region): the per-stage kernel times from HIP
+events recorded on the launch stream during the timed steps, the roofline of
+the dominant kernel, the FP32 path's relative L2 error against the full-FP64
+GPU form and against the CPU FP64 oracle on a sample of lines, and the CPU
+oracle's own throughput on that sample (cpu_baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+adj NUFFT projector Mpts/s at 256³, rel-L2≤1e-4; FP32 vs FP64 form"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def alg_bytes(N, K, M, cb, touched):
+    """Algorithmic HBM bytes per launch of each stage (cb = bytes per complex)."""
+    fft = cb * (N ** 3 + 2 * N * N * K + 2 * N * K * K + K ** 3)
+    return {
+        "pad_fft": fft,                       # pruned passes, deapodization fused
+        "interp": cb * (touched + M),          # touched grid cells once + M outputs
+        "radial": 2 * cb * M,                  # read + write M
+        "radial_adj": 2 * cb * M,
+        "spread": cb * (M + K ** 3),           # read M + write every grid cell once
+        "ifft_crop": fft,
+        "reduce": 0,                           # partial-tile sums (not algorithmic)
+    }
+
+
+def cpu_oracle_baseline(x, dirs, n_r, N, K, J, sample_lines):
+    """Time the CPU FP64 oracle on the full grid with a sample of the lines.
+
+    The grid-size work (oversampled FFT and inverse FFT) is timed in full;
+    the point work (interpolation, radial stage and its adjoint, spreading) is
+    timed on `sample_lines` lines and scaled to all lines.  Returns the
+    timing record and the oracle's sample outputs."""
+    import numpy as np
+    from oracle import nufft, radial
+
+    prm = nufft.Params(N, K, J)
+    om = radial.points(dirs[sample_lines], n_r)
+    t = {}
+    t0 = time.perf_counter()
+    Y = nufft.oversampled_spectrum(x.astype(np.complex128), prm)
+    t["fft"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    G = nufft.interpolate(Y, om, prm)
+    t["interp"] = time.perf_counter() - t0
+    del Y
+    t0 = time.perf_counter()
+    D = radial.forward(G, n_r)
+    t["radial"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Gt = radial.adjoint(D, n_r)
+    t["radial_adj"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Yt = nufft.spread(Gt, om, prm)
+    t["spread"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    v = nufft.crop_scale(nufft.inverse_spectrum(Yt, prm), prm)
+    t["ifft_crop"] = time.perf_counter() - t0
+    return t, D, v
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c3", choices=["c2", "c3"])
+    ap.add_argument("--kernel", default="kb", choices=["kb", "minmax"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-form comparison")
+    ap.add_argument("--cpu-sample-lines", type=int, default=640)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the projector runs "
+              "on a single MI355X and has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1605_05231_amd as pkg
+    import synthetic
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    W = synthetic.WORKLOADS[args.workload]
+    N, K, J, n_r = W.N, W.K, W.J, W.n_r
+    dirs = W.directions()
+    M = W.M
+    log(f"[bench] workload {W.name}: N={N} K={K} J={J} lines={len(dirs)} n_r={n_r} M={M}")
+    t0 = time.perf_counter()
+    x_np = W.volume()
+    log(f"[bench] phantom {time.perf_counter() - t0:.1f}s")
+
+    t0 = time.perf_counter()
+    plan = pkg.Plan(N, K, J, dirs=dirs, n_r=n_r, kernel=args.kernel, dtype=torch.complex64)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    log(f"[bench] plan {plan_s:.2f}s")
+
+    x = torch.from_numpy(x_np.astype(np.complex64)).cuda()
+    D = torch.empty((len(dirs), n_r), dtype=torch.complex64, device="cuda")
+    V = torch.empty((N, N, N), dtype=torch.complex64, device="cuda")
+
+    def step():
+        plan.forward(x, out=D)
+        plan.adjoint(D, out=V)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.stage_times()  # clear
+    plan.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    plan.set_timing(False)
+    st = plan.stage_times()
+    ms_per_step = wall * 1e3 / args.steps
+    value = M / (ms_per_step * 1e-3) / 1e6
+    log(f"[bench] {ms_per_step:.3f} ms/step -> {value:.1f} Mpts/s")
+    stage_avg = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in st.items()}
+    log("[bench] stage avg ms: " + ", ".join(f"{k}={v:.3f}" for k, v in stage_avg.items()))
+
+    # touched grid cells: spread positive weights of all-ones input and count nonzeros
+    ones = torch.ones(M, dtype=torch.complex64, device="cuda")
+    grid = torch.empty(K ** 3, dtype=torch.complex64, device="cuda")
+    plan.stage(pkg.STAGE_SPREAD, ones, grid)
+    touched = int(torch.count_nonzero(grid.real).item())
+    del grid, ones
+    ab = alg_bytes(N, K, M, 8, touched)
+    single = ["interp", "spread", "radial", "radial_adj"]
+    dom = max(single, key=lambda k: stage_avg[k])
+    achieved = ab[dom] / (stage_avg[dom] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "alg_bytes_per_launch": ab[dom], "avg_launch_ms": round(stage_avg[dom], 4)}
+    stages = {k: {"avg_ms": round(stage_avg[k], 4),
+                  "alg_GBps": round(ab[k] / (stage_avg[k] * 1e-3) / 1e9, 1) if stage_avg[k] and ab[k] else None}
+              for k in stage_avg}
+
+    result = {
+        "metric": METRIC, "value": round(value, 2), "unit": "Mpts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{W.name}: {N}^3 volume, K={K}^3, J={J} {args.kernel}, "
+                               f"{W.n_phi}x{W.n_theta} lines x {n_r} samples",
+                   "N": N, "K": K, "J": J, "kernel": args.kernel, "points": M,
+                   "step": "forward (derivative-Radon) + adjoint"},
+        "roofline": roofline,
+        "stages": stages,
+        "touched_cells": touched,
+        "plan_s": round(plan_s, 2),
+    }
+
+    # FP64 form: speed and the FP32 path's error against it
+    if not args.no_fp64:
+        del plan
+        torch.cuda.empty_cache()
+        D32 = D.clone()
+        V32 = V.clone()
+        del D, V
+        p64 = pkg.Plan(N, K, J, dirs=dirs, n_r=n_r, kernel=args.kernel, dtype=torch.complex128)
+        x64 = torch.from_numpy(x_np.astype(np.complex128)).cuda()
+        D64 = p64.forward(x64)
+        V64 = p64.adjoint(D64)
+        # the FP32 adjoint above consumed the FP32 forward's output; compare like with like
+        V64_from32 = p64.adjoint(D32.to(torch.complex128))
+        torch.cuda.synchronize()
+        n64 = max(2, args.steps // 4)
+        t0 = time.perf_counter()
+        for _ in range(n64):
+            p64.forward(x64, out=D64)
+            p64.adjoint(D64, out=V64)
+        torch.cuda.synchronize()
+        ms64 = (time.perf_counter() - t0) * 1e3 / n64
+        d = (D32.to(torch.complex128) - D64)
+        ef = float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(D64))
+        mf = float(d.abs().max() / D64.abs().max())
+        va = (V32.to(torch.complex128) - V64_from32)
+        ea = float(torch.linalg.vector_norm(va) / torch.linalg.vector_norm(V64_from32))
+        ma = float(va.abs().max() / V64_from32.abs().max())
+        result["fp64_form"] = {"value": round(M / (ms64 * 1e-3) / 1e6, 2), "ms_per_step": round(ms64, 3),
+                               "speedup_fp32_over_fp64": round(ms64 / ms_per_step, 2)}
+        result["accuracy_vs_fp64_form"] = {"fwd_rel_l2": ef, "fwd_max_rel": mf,
+                                           "adj_rel_l2": ea, "adj_max_rel": ma}
+        log(f"[bench] FP64 form {ms64:.2f} ms/step; FP32 vs FP64 fwd {ef:.2e} adj {ea:.2e}")
+        del p64, x64, D64, V64, V64_from32, d, va
+        torch.cuda.empty_cache()
+        D, V = D32, V32
+
+    if not args.no_cpu_baseline:
+        L = len(dirs)
+        ns = min(args.cpu_sample_lines, L)
+        sample = np.unique(np.linspace(0, L - 1, ns).round().astype(int))
+        log(f"[bench] CPU oracle on {len(sample)} of {L} lines ...")
+        t, Ds, vs = cpu_oracle_baseline(x_np.astype(np.complex64).astype(np.complex128), dirs, n_r,
+                                         N, K, J, sample)
+        Ms = len(sample) * n_r
+        scale = M / Ms
+        est = t["fft"] + t["ifft_crop"] + (t["interp"] + t["radial"] + t["radial_adj"] + t["spread"]) * scale
+        spent = sum(t.values())
+        cores = 1  # numpy's FFT, bincount and elementwise loops run on one thread
+        result["cpu_baseline"] = {
+            "value": round(M / est / 1e6, 4), "unit": "Mpts/s", "cores": cores, "kind": "oracle",
+            "sample": f"{W.name} grid in full (FFT + inverse FFT timed once: {t['fft']:.1f}s + "
+                      f"{t['ifft_crop']:.1f}s); point stages on {len(sample)} of {L} lines "
+                      f"({Ms} points) scaled by {scale:.1f}; {spent:.1f}s of CPU time",
+            "stage_s": {k: round(v, 3) for k, v in t.items()},
+            "gpu_speedup": round((M / est / 1e6) and value / (M / est / 1e6), 1),
+        }
+        # parity on the sample: forward lines and the adjoint of those lines alone
+        Dg = D.reshape(L, n_r)[torch.from_numpy(sample).cuda()].cpu().numpy().reshape(-1)
+        ef = float(np.linalg.norm(Dg - Ds) / np.linalg.norm(Ds))
+        Din = torch.zeros((L, n_r), dtype=torch.complex64, device="cuda")
+        Din[torch.from_numpy(sample).cuda()] = torch.from_numpy(Ds.reshape(-1, n_r).astype(np.complex64)).cuda()
+        p32 = pkg.Plan(N, K, J, dirs=dirs, n_r=n_r, kernel=args.kernel, dtype=torch.complex64)
+        vg = p32.adjoint(Din).cpu().numpy()
+        vs32 = vs  # oracle adjoint of the FP64 sample lines
+        ea = float(np.linalg.norm(vg - vs32) / np.linalg.norm(vs32))
+        result["accuracy_vs_oracle_sample"] = {"fwd_rel_l2": ef, "adj_rel_l2": ea,
+                                               "lines": int(len(sample))}
+        log(f"[bench] oracle sample: fwd {ef:.2e} adj {ea:.2e}; CPU {M / est / 1e6:.3f} Mpts/s")
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -64,16 +64,27 @@ def voxel_coords(N: int) -> np.ndarray:
 
 
 def voxelize(ells: list[Ellipsoid], N: int) -> np.ndarray:
-    """Point-sampled indicator ellipsoids on the N^3 voxel grid (float64)."""
+    """Point-sampled indicator ellipsoids on the N^3 voxel grid (float64).
+
+    Each ellipsoid is evaluated only inside the box that holds its
+    circumscribed ball (radius = largest semi-axis); outside it the indicator
+    is zero, so the result equals evaluating it everywhere."""
     u = voxel_coords(N)
-    U0, U1, U2 = np.meshgrid(u, u, u, indexing="ij")
-    pts = np.stack([U0, U1, U2], axis=-1)  # (N,N,N,3)
     vol = np.zeros((N, N, N), dtype=np.float64)
     for e in ells:
-        d = pts - e.center
+        r = float(np.max(e.axes))
+        sl = []
+        for d in range(3):
+            lo = int(np.floor((e.center[d] - r) * N / 2 + N // 2)) - 1
+            hi = int(np.ceil((e.center[d] + r) * N / 2 + N // 2)) + 2
+            sl.append(slice(max(lo, 0), min(hi, N)))
+        if any(s.start >= s.stop for s in sl):
+            continue
+        U0, U1, U2 = np.meshgrid(u[sl[0]], u[sl[1]], u[sl[2]], indexing="ij")
+        d = np.stack([U0, U1, U2], axis=-1) - e.center
         loc = d @ e.rot  # coordinates along the ellipsoid axes
         q = np.sum((loc / e.axes) ** 2, axis=-1)
-        vol += e.density * (q <= 1.0)
+        vol[sl[0], sl[1], sl[2]] += e.density * (q <= 1.0)
     return vol
 
 

@@ -37,6 +37,7 @@ CASES = [
     ("n16_k32_j8_minmax", 16, 32, 8, "minmax", 6, 3, 32),
     ("n32_k64_j6_minmax", 32, 64, 6, "minmax", 8, 4, 64),
     ("n24_k48_j6_fewlines", 24, 48, 6, "kb", 5, 5, 48),
+    ("n8_k16_j4_onetile", 8, 16, 4, "kb", 4, 3, 16),
 ]
 
 
@@ -262,3 +263,27 @@ def test_python_binding_rejects_bad_tensors():
     v = torch.zeros(2 * 16 ** 3, dtype=torch.complex64, device="cuda")[::2]
     with pytest.raises(ValueError):
         plan.forward(v)
+
+
+@pytest.mark.parametrize("tile,maxpts", [(8, 256), (16, 256), (8, 4096)])
+def test_tiling_and_split_tiles(monkeypatch, tile, maxpts):
+    """Small tasks force split (heavy) output tiles and their partial-tile
+    reduction; both tile edges must give the same operator."""
+    require_gpu()
+    from paper_1605_05231_amd import Plan
+    import torch
+    monkeypatch.setenv("NUFFTCT_TILE", str(tile))
+    monkeypatch.setenv("NUFFTCT_MAXPTS", str(maxpts))
+    N, K, J, n_r = 32, 64, 6, 64
+    dirs = synthetic.line_directions(synthetic.azimuths(24), synthetic.polar_angles(12))
+    prm = nufft.Params(N, K, J)
+    rng = np.random.default_rng(tile + maxpts)
+    x = (synthetic.ellipsoid_phantom(N, 8, 5) + 0j).astype(np.complex64).astype(complex)
+    y = (rng.standard_normal(len(dirs) * n_r) + 1j * rng.standard_normal(len(dirs) * n_r)).astype(np.complex64).astype(complex)
+    plan = Plan(N, K, J, dirs=dirs, n_r=n_r)
+    f = to_host(plan.forward(to_dev(x, torch.complex64)))
+    a = to_host(plan.adjoint(to_dev(y, torch.complex64)))
+    ef = rel_l2(f, projector.forward(x, dirs, n_r, prm))
+    ea = rel_l2(a, projector.adjoint(y, dirs, n_r, prm))
+    say(f"tile={tile} maxpts={maxpts} fwd={ef:.2e} adj={ea:.2e}")
+    assert ef < 1e-5 and ea < 1e-5
