@@ -43,9 +43,9 @@ def alg_bytes(N, K, M, cb, touched):
         "interp": cb * (touched + M),          # touched grid cells once + M outputs
         "radial": 2 * cb * M,                  # read + write M
         "radial_adj": 2 * cb * M,
-        "spread": cb * (M + K ** 3),           # read M + write every grid cell once
+        "spread": cb * M,                      # read M (halo partials are not algorithmic)
         "ifft_crop": fft,
-        "reduce": 0,                           # partial-tile sums (not algorithmic)
+        "merge": cb * K ** 3,                  # write every grid cell once
     }
 
 
@@ -94,6 +94,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-form comparison")
     ap.add_argument("--cpu-sample-lines", type=int, default=640)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -123,6 +125,14 @@ def main():
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
     log(f"[bench] plan {plan_s:.2f}s")
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("[bench] copy calibration: 1 GiB read + 1 GiB written by one copy kernel")
 
     x = torch.from_numpy(x_np.astype(np.complex64)).cuda()
     D = torch.empty((len(dirs), n_r), dtype=torch.complex64, device="cuda")
@@ -158,7 +168,7 @@ def main():
     touched = int(torch.count_nonzero(grid.real).item())
     del grid, ones
     ab = alg_bytes(N, K, M, 8, touched)
-    single = ["interp", "spread", "radial", "radial_adj"]
+    single = ["interp", "spread", "merge", "radial", "radial_adj"]
     dom = max(single, key=lambda k: stage_avg[k])
     achieved = ab[dom] / (stage_avg[dom] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,

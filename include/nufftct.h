@@ -150,17 +150,17 @@ int nufftct_plan_destroy(nufftct_plan* plan);
 int nufftct_plan_info(const nufftct_plan* plan, int64_t* N, int64_t* K, int* J,
                       int64_t* M, int64_t* n_r, int* precision, int64_t* workspace_bytes);
 
-/* timing slot of the kernel that sums the partial tiles of split spread tiles */
-#define NUFFTCT_TIMING_REDUCE 6
+/* timing slot of the kernel that merges the spread's per-task halo tiles into the grid */
+#define NUFFTCT_TIMING_MERGE 6
 
 /*
  * Per-stage timing with HIP events recorded on the call's stream.
  * nufftct_set_timing(plan, 1) starts accumulating; nufftct_get_stage_times
  * synchronises on the recorded events and writes, for each slot s in 0..n-1
- * (NUFFTCT_STAGE_* order, then NUFFTCT_TIMING_REDUCE; at most 8 slots), the
+ * (NUFFTCT_STAGE_* order, then NUFFTCT_TIMING_MERGE; at most 8 slots), the
  * summed milliseconds to ms[s] and the number of timed launches to count[s]
  * (either may be NULL), then resets.  Slots INTERP, RADIAL, RADIAL_ADJ,
- * SPREAD and REDUCE each time exactly one kernel; PAD_FFT and IFFT_CROP time
+ * SPREAD and MERGE each time exactly one kernel; PAD_FFT and IFFT_CROP time
  * their three FFT-pass kernels together.
  */
 int nufftct_set_timing(nufftct_plan* plan, int enable);

@@ -253,20 +253,32 @@ def _autograd():
 
     class NufftProjector(torch.autograd.Function):
         """y = A x with A the plan's forward (derivative-Radon by default); the
-        backward applies the hand-written adjoint A^H.  Real inputs get the
-        real part of A^H g as their gradient."""
+        backward applies the hand-written adjoint A^H.  x may be one volume
+        (N, N, N) or a batch (B, N, N, N) sharing the plan's geometry.  Real
+        inputs get the real part of A^H g as their gradient."""
 
         @staticmethod
         def forward(ctx, x, plan, radial=True, deriv=True):
             ctx.plan, ctx.radial, ctx.deriv = plan, radial, deriv
             ctx.real_input = not x.is_complex()
             xc = x.to(plan.dtype).contiguous()
-            return plan.forward(xc, radial=radial, deriv=deriv)
+            if xc.dim() == 3:
+                return plan.forward(xc, radial=radial, deriv=deriv)
+            out = torch.empty((xc.shape[0],) + plan.out_shape, dtype=plan.dtype, device=xc.device)
+            for b in range(xc.shape[0]):
+                plan.forward(xc[b], out=out[b], radial=radial, deriv=deriv)
+            return out
 
         @staticmethod
         def backward(ctx, g):
             plan = ctx.plan
-            gx = plan.adjoint(g.to(plan.dtype).contiguous(), radial=ctx.radial, deriv=ctx.deriv)
+            gc = g.to(plan.dtype).contiguous()
+            if gc.dim() == len(plan.out_shape):
+                gx = plan.adjoint(gc, radial=ctx.radial, deriv=ctx.deriv)
+            else:
+                gx = torch.empty((gc.shape[0],) + plan.vol_shape, dtype=plan.dtype, device=gc.device)
+                for b in range(gc.shape[0]):
+                    plan.adjoint(gc[b], out=gx[b], radial=ctx.radial, deriv=ctx.deriv)
             if ctx.real_input:
                 gx = gx.real
             return gx, None, None, None

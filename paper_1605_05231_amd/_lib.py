@@ -13,8 +13,8 @@ FP32, FP64 = 0, 1
 RADIAL, DERIV = 1, 2
 DERIV_RADIAL = RADIAL | DERIV
 STAGE_PAD_FFT, STAGE_INTERP, STAGE_RADIAL, STAGE_RADIAL_ADJ, STAGE_SPREAD, STAGE_IFFT_CROP = range(6)
-STAGE_NAMES = ["pad_fft", "interp", "radial", "radial_adj", "spread", "ifft_crop", "reduce"]
-TIMING_REDUCE = 6
+STAGE_NAMES = ["pad_fft", "interp", "radial", "radial_adj", "spread", "ifft_crop", "merge"]
+TIMING_MERGE = 6
 
 # every entry point declared in include/nufftct.h: name -> (restype, argtypes)
 _p = C.c_void_p

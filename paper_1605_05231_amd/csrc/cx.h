@@ -33,8 +33,18 @@ __device__ __forceinline__ cx<T> cmul_si(cx<T> a) {
 // number of XCDs of gfx950; workgroups are dispatched round-robin across them
 #define NUFFTCT_NUM_XCD 8
 
-// Map a linear block index to a task so that each XCD receives a contiguous
-// range of tasks (neighbouring tiles share their halos through that XCD's L2).
-__device__ __forceinline__ int64_t xcd_task(int64_t b, int64_t per_xcd) {
-  return (b % NUFFTCT_NUM_XCD) * per_xcd + b / NUFFTCT_NUM_XCD;
+// Contiguous task ranges, one per XCD, cut on the host so that each range
+// holds about the same number of points.  Block b runs on XCD b % 8 and takes
+// the (b / 8)-th task of that XCD's range, so neighbouring tiles (which share
+// halo cells) go through the same L2 and every XCD gets an equal share of work.
+struct XcdSplit {
+  int32_t start[NUFFTCT_NUM_XCD + 1];
+  int32_t max_len;  // longest range; the grid has 8 * max_len blocks
+};
+
+// Task of block b, or -1 when b is past the end of its XCD's range.
+__device__ __forceinline__ int64_t xcd_task(int64_t b, const XcdSplit& xs) {
+  const int x = (int)(b % NUFFTCT_NUM_XCD);
+  const int64_t t = xs.start[x] + b / NUFFTCT_NUM_XCD;
+  return t < xs.start[x + 1] ? t : -1;
 }

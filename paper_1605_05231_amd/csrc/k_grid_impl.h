@@ -9,8 +9,10 @@
 // TILE cells dividing K) and processed tile by tile.  Interpolation: one
 // workgroup per task (a bin and up to max_pts of its points) stages the tile
 // plus its (J-1)-cell halo, S^3 cells with S = TILE + J - 1, in LDS once;
-// every point then reads its J^3 taps there.  Spreading is owner-computes
-// (see k_spread): no global atomics, every grid cell written once.
+// every point then reads its J^3 taps there.  Spreading uses the same tasks:
+// each accumulates its halo tile in LDS and stores it as a partial; an
+// owner-computes merge sums the partials into the grid.  No global atomics;
+// every grid cell is written once.
 // The tap index math runs in FP64 without contraction so that it reproduces
 // the host binning bit for bit; in the interpolation a point whose taps still
 // fall outside the staged tile takes a global-memory path.
@@ -26,6 +28,7 @@
 namespace kgrid {
 
 constexpr int NT = 256;
+constexpr int NT_SPREAD = 1024;
 
 template <typename T>
 __device__ __forceinline__ void lds_add(T* a, T v) {
@@ -93,12 +96,12 @@ __global__ __launch_bounds__(NT) void k_interp(const cx<T>* __restrict__ grid,
                                                cx<T>* __restrict__ out,
                                                const int32_t* __restrict__ perm,
                                                const TileTask* __restrict__ tasks,
-                                               int64_t ntasks, int64_t per_xcd, PointGeom g,
+                                               XcdSplit xs, PointGeom g,
                                                int nb, WeightPoly<T, DEG> P) {
   constexpr int S = TILE + J - 1;
   __shared__ cx<T> tile[S * S * S];
-  const int64_t task_id = xcd_task(blockIdx.x, per_xcd);
-  if (task_id >= ntasks) return;
+  const int64_t task_id = xcd_task(blockIdx.x, xs);
+  if (task_id < 0) return;
   const TileTask tk = tasks[task_id];
   const int K = g.K;
   const int b2 = tk.bin % nb, b1 = (tk.bin / nb) % nb, b0 = tk.bin / (nb * nb);
@@ -173,122 +176,135 @@ __global__ __launch_bounds__(NT) void k_interp(const cx<T>* __restrict__ grid,
 }
 
 // ---------------------------------------------------------------------------
-// Owner-computes spreading: one task per output tile (or per chunk of a heavy
-// tile's points).  The tile (TILE^3 cells, no halo) accumulates in LDS the
-// contributions of every point whose footprint reaches it: the points of its
-// own bin and the spilling points of the 7 lower-neighbour bins, listed as
-// segments of the permutation.  The finished tile is written with plain
-// coalesced stores, zeros included, so the grid needs no clearing and no
-// global atomics; a split tile writes a partial that k_reduce_partials sums
-// in a fixed order.
+// Spreading, phase 1: one workgroup per task accumulates all J^3 taps of its
+// points into the task's halo tile (S^3 cells, S = TILE + J - 1) in LDS, then
+// writes the halo tile to the task's partial slot with plain stores.  Every
+// point is visited once and every tap lands inside the halo.
+//
+// LDS accumulation (f32 LDS atomic adds run ~8x slower than 64-bit ones on
+// gfx950):
+//   FP32 path: each contribution is quantised to an integer of magnitude
+//     < 2^31 with the task's scale 2^28 / max|component of its inputs| and
+//     summed exactly in 64-bit integers (ds_add_u64), so the per-contribution
+//     error is <= 2^-29 of the task's largest input and the sum is
+//     independent of the order of the atomics (bitwise reproducible).
+//   FP64 form: FP64 atomic adds (ds_add_f64).
 template <typename T, int J, int TILE, bool CW, int DEG>
-__global__ __launch_bounds__(NT) void k_spread(const cx<T>* __restrict__ in,
-                                               cx<T>* __restrict__ grid,
-                                               cx<double>* __restrict__ partials,
-                                               const int32_t* __restrict__ perm,
-                                               const SpreadTask* __restrict__ tasks,
-                                               const SpreadSeg* __restrict__ segs,
-                                               int64_t ntasks, int64_t per_xcd, PointGeom g,
-                                               int nb, WeightPoly<T, DEG> P) {
-  constexpr int TT = TILE * TILE * TILE;
-  constexpr int RP = TILE + 1;  // padded row pitch (breaks r2-only bank mapping)
-  // FP64 accumulators: LDS f64 atomic adds run several times faster than f32
-  // ones on gfx950 and make the per-tile sums exact to FP32 output precision
-  __shared__ cx<double> tile[TILE * TILE * RP];
-  const int64_t task_id = xcd_task(blockIdx.x, per_xcd);
-  if (task_id >= ntasks) return;
-  const SpreadTask tk = tasks[task_id];
-  const int K = g.K;
-  const int t2 = tk.tile % nb, t1 = (tk.tile / nb) % nb, t0 = tk.tile / (nb * nb);
-  for (int idx = threadIdx.x; idx < TILE * TILE * RP; idx += NT) tile[idx] = cx<double>{0, 0};
-  __syncthreads();
-  int base = 0;
-  for (int s = tk.seg_begin; s < tk.seg_end; ++s) {
-    const SpreadSeg sg = segs[s];
-    const int lo = max(tk.p_lo, base) - base;
-    const int hi = min(tk.p_hi, base + sg.count) - base;
-    base += sg.count;
-    if (lo >= hi) continue;
-    const int d0 = (sg.delta >> 2) & 1, d1 = (sg.delta >> 1) & 1, d2 = sg.delta & 1;
-    // origin of the source bin's tile
-    const int so0 = ((t0 - d0 + nb) % nb) * TILE;
-    const int so1 = ((t1 - d1 + nb) % nb) * TILE;
-    const int so2 = ((t2 - d2 + nb) % nb) * TILE;
-    for (int i = lo + (int)threadIdx.x; i < hi; i += NT) {
-      const int p = perm[sg.start + i];
-      const cx<T> v = in[p];
-      int first[3];
-      double frac[3];
-      point_taps(g, p, J, first, frac);
-      T w0r[J], w0i[J], w1r[J], w1i[J], w2r[J], w2i[J];
-      axis_weights<T, J, DEG, CW>(P, frac[0], w0r, w0i);
-      axis_weights<T, J, DEG, CW>(P, frac[1], w1r, w1i);
-      axis_weights<T, J, DEG, CW>(P, frac[2], w2r, w2i);
-      // first tap relative to this tile's origin (negative when it lies in the
-      // lower neighbour tile)
-      int q0 = first[0] - so0, q1 = first[1] - so1, q2 = first[2] - so2;
-      q0 += q0 < 0 ? K : 0;
-      q1 += q1 < 0 ? K : 0;
-      q2 += q2 < 0 ? K : 0;
-      const int l0 = q0 - d0 * TILE, l1 = q1 - d1 * TILE, l2 = q2 - d2 * TILE;
+__global__ __launch_bounds__(NT_SPREAD) void k_spread(const cx<T>* __restrict__ in,
+                                                      cx<T>* __restrict__ partials,
+                                                      const int32_t* __restrict__ perm,
+                                                      const TileTask* __restrict__ tasks,
+                                                      XcdSplit xs, PointGeom g, int nb,
+                                                      WeightPoly<T, DEG> P) {
+  constexpr bool FIXED = sizeof(T) == 4;
+  constexpr int S = TILE + J - 1;
+  constexpr int SS = S * S * S;
+  __shared__ cx<double> acc[SS];  // FP64 sums, or (re, im) int64 pairs on the FP32 path
+  __shared__ unsigned int s_maxbits;
+  long long* acci = reinterpret_cast<long long*>(acc);
+  const int64_t task_id = xcd_task(blockIdx.x, xs);
+  if (task_id < 0) return;
+  const TileTask tk = tasks[task_id];
+  const int b2 = tk.bin % nb, b1 = (tk.bin / nb) % nb, b0 = tk.bin / (nb * nb);
+  const int o0 = b0 * TILE, o1 = b1 * TILE, o2 = b2 * TILE;
+  for (int idx = threadIdx.x; idx < SS; idx += NT_SPREAD) acc[idx] = cx<double>{0, 0};
+  T scale = (T)1;
+  if constexpr (FIXED) {
+    if (threadIdx.x == 0) s_maxbits = 0u;
+    __syncthreads();
+    float m = 0.f;
+    for (int i = threadIdx.x; i < tk.count; i += NT_SPREAD) {
+      const cx<T> v = in[perm[tk.start + i]];
+      m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+    }
+    // non-negative floats order like their bit patterns
+    atomicMax(&s_maxbits, __float_as_uint(m));
+    __syncthreads();
+    const float vmax = __uint_as_float(s_maxbits);
+    scale = vmax > 0.f ? 268435456.0f / vmax : 1.0f;  // 2^28 / max
+  } else {
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < tk.count; i += NT_SPREAD) {
+    const int p = perm[tk.start + i];
+    cx<T> v = in[p];
+    v = cx<T>{v.x * scale, v.y * scale};
+    int first[3];
+    double frac[3];
+    point_taps(g, p, J, first, frac);
+    const int l0 = first[0] - o0, l1 = first[1] - o1, l2 = first[2] - o2;
+    // the host bins with the same FP64 arithmetic, so every point of the task
+    // lies in its tile; the check only keeps LDS accesses in bounds
+    if ((unsigned)l0 >= (unsigned)TILE || (unsigned)l1 >= (unsigned)TILE ||
+        (unsigned)l2 >= (unsigned)TILE)
+      continue;
+    T w0r[J], w0i[J], w1r[J], w1i[J], w2r[J], w2i[J];
+    axis_weights<T, J, DEG, CW>(P, frac[0], w0r, w0i);
+    axis_weights<T, J, DEG, CW>(P, frac[1], w1r, w1i);
+    axis_weights<T, J, DEG, CW>(P, frac[2], w2r, w2i);
 #pragma unroll
-      for (int a = 0; a < J; ++a) {
-        const int r0 = l0 + a;
-        if ((unsigned)r0 >= (unsigned)TILE) continue;
-        // conj(w) for the transpose
-        const cx<T> va = CW ? cmulc(v, cx<T>{w0r[a], w0i[a]}) : cx<T>{w0r[a] * v.x, w0r[a] * v.y};
+    for (int a = 0; a < J; ++a) {
+      // conj(w) for the transpose
+      const cx<T> va = CW ? cmulc(v, cx<T>{w0r[a], w0i[a]}) : cx<T>{w0r[a] * v.x, w0r[a] * v.y};
 #pragma unroll
-        for (int b = 0; b < J; ++b) {
-          const int r1 = l1 + b;
-          if ((unsigned)r1 >= (unsigned)TILE) continue;
-          const cx<T> vb =
-              CW ? cmulc(va, cx<T>{w1r[b], w1i[b]}) : cx<T>{w1r[b] * va.x, w1r[b] * va.y};
-          cx<double>* row = &tile[(r0 * TILE + r1) * RP];
+      for (int b = 0; b < J; ++b) {
+        const cx<T> vb =
+            CW ? cmulc(va, cx<T>{w1r[b], w1i[b]}) : cx<T>{w1r[b] * va.x, w1r[b] * va.y};
+        const int row = ((l0 + a) * S + (l1 + b)) * S + l2;
 #pragma unroll
-          for (int c = 0; c < J; ++c) {
-            const int r2 = l2 + c;
-            if ((unsigned)r2 >= (unsigned)TILE) continue;
-            const cx<T> u =
-                CW ? cmulc(vb, cx<T>{w2r[c], w2i[c]}) : cx<T>{w2r[c] * vb.x, w2r[c] * vb.y};
-            lds_add(&row[r2].x, (double)u.x);
-            lds_add(&row[r2].y, (double)u.y);
+        for (int c = 0; c < J; ++c) {
+          const cx<T> u =
+              CW ? cmulc(vb, cx<T>{w2r[c], w2i[c]}) : cx<T>{w2r[c] * vb.x, w2r[c] * vb.y};
+          if constexpr (FIXED) {
+            lds_add(&acci[2 * (row + c)], (long long)__float2int_rn(u.x));
+            lds_add(&acci[2 * (row + c) + 1], (long long)__float2int_rn(u.y));
+          } else {
+            lds_add(&acc[row + c].x, (double)u.x);
+            lds_add(&acc[row + c].y, (double)u.y);
           }
         }
       }
     }
   }
   __syncthreads();
-  if (tk.slot < 0) {
-    const int o0 = t0 * TILE, o1 = t1 * TILE, o2 = t2 * TILE;
-    for (int idx = threadIdx.x; idx < TT; idx += NT) {
-      const int i2 = idx % TILE, i1 = (idx / TILE) % TILE, i0 = idx / (TILE * TILE);
-      const cx<double> v = tile[(i0 * TILE + i1) * RP + i2];
-      grid[((int64_t)(o0 + i0) * K + (o1 + i1)) * K + (o2 + i2)] = cx<T>{(T)v.x, (T)v.y};
-    }
+  cx<T>* dst = partials + task_id * (int64_t)SS;
+  if constexpr (FIXED) {
+    const double inv = 1.0 / (double)scale;
+    for (int idx = threadIdx.x; idx < SS; idx += NT_SPREAD)
+      dst[idx] = cx<T>{(T)((double)acci[2 * idx] * inv), (T)((double)acci[2 * idx + 1] * inv)};
   } else {
-    cx<double>* dst = partials + (int64_t)tk.slot * TT;
-    for (int idx = threadIdx.x; idx < TT; idx += NT) {
-      const int i2 = idx % TILE, i1 = (idx / TILE) % TILE, i0 = idx / (TILE * TILE);
-      dst[idx] = tile[(i0 * TILE + i1) * RP + i2];
-    }
+    for (int idx = threadIdx.x; idx < SS; idx += NT_SPREAD)
+      dst[idx] = cx<T>{(T)acc[idx].x, (T)acc[idx].y};
   }
 }
 
-// Sum the partial tiles of each split output tile, in slot order, into the grid.
+// Spreading, phase 2 (owner computes): one workgroup per output tile sums, for
+// each of its cells, the halo partials that cover it -- those of every task of
+// its own bin and of the 7 lower-neighbour bins (their halos reach J-1 cells
+// into this tile) -- in a fixed order, and writes every cell of the grid once.
 template <typename T>
-__global__ __launch_bounds__(NT) void k_reduce_partials(const cx<double>* __restrict__ partials,
-                                                        cx<T>* __restrict__ grid,
-                                                        const HeavyTile* __restrict__ heavy,
-                                                        int nb, int K, int TILE) {
-  const HeavyTile h = heavy[blockIdx.x];
+__global__ __launch_bounds__(NT) void k_merge(const cx<T>* __restrict__ partials,
+                                              const int32_t* __restrict__ bin_tasks,
+                                              cx<T>* __restrict__ grid, int nb, int K, int TILE,
+                                              int J) {
+  const int S = TILE + J - 1;
+  const int64_t SS = (int64_t)S * S * S;
+  const int tile = blockIdx.x;
+  const int t2 = tile % nb, t1 = (tile / nb) % nb, t0 = tile / (nb * nb);
   const int TT = TILE * TILE * TILE;
-  const int t2 = h.tile % nb, t1 = (h.tile / nb) % nb, t0 = h.tile / (nb * nb);
   for (int idx = threadIdx.x; idx < TT; idx += NT) {
-    cx<double> acc = {0, 0};
-    for (int s = h.slot_begin; s < h.slot_end; ++s) acc = cadd(acc, partials[(int64_t)s * TT + idx]);
     const int i2 = idx % TILE, i1 = (idx / TILE) % TILE, i0 = idx / (TILE * TILE);
-    grid[((int64_t)(t0 * TILE + i0) * K + (t1 * TILE + i1)) * K + (t2 * TILE + i2)] =
-        cx<T>{(T)acc.x, (T)acc.y};
+    cx<T> sum = {0, 0};
+    for (int delta = 0; delta < 8; ++delta) {
+      const int d0 = (delta >> 2) & 1, d1 = (delta >> 1) & 1, d2 = delta & 1;
+      // position of this cell inside the halo of bin (tile - delta)
+      const int q0 = i0 + d0 * TILE, q1 = i1 + d1 * TILE, q2 = i2 + d2 * TILE;
+      if (q0 >= S || q1 >= S || q2 >= S) continue;
+      const int sb = (((t0 - d0 + nb) % nb) * nb + (t1 - d1 + nb) % nb) * nb + (t2 - d2 + nb) % nb;
+      const int64_t off = ((int64_t)q0 * S + q1) * S + q2;
+      for (int t = bin_tasks[sb]; t < bin_tasks[sb + 1]; ++t) sum = cadd(sum, partials[t * SS + off]);
+    }
+    grid[((int64_t)(t0 * TILE + i0) * K + (t1 * TILE + i1)) * K + (t2 * TILE + i2)] = sum;
   }
 }
 
@@ -307,9 +323,8 @@ struct PolyOf<double> {
 };
 
 template <typename T, int J, int TILE>
-constexpr bool tile_fits() {
-  return (TILE + J - 1) * (TILE + J - 1) * (TILE + J - 1) * (int)sizeof(cx<T>) <= 96 * 1024 &&
-         J - 1 <= TILE;
+constexpr bool tile_fits() {  // the spread's FP64 halo tile must fit in LDS
+  return (TILE + J - 1) * (TILE + J - 1) * (TILE + J - 1) * 16 <= 160 * 1024 && J - 1 <= TILE;
 }
 
 template <typename T, int J, int TILE, bool CW, bool SPREAD>
@@ -319,17 +334,15 @@ hipError_t launch_one(const nufftct_plan& p, const void* src, void* dst, hipStre
   } else {
     constexpr int DEG = PolyOf<T>::DEG;
     const auto& P = PolyOf<T>::get(p);
-    const int64_t per = (p.ntasks + NUFFTCT_NUM_XCD - 1) / NUFFTCT_NUM_XCD;
-    const dim3 grd((unsigned)(per * NUFFTCT_NUM_XCD));
+    const dim3 grd((unsigned)((int64_t)p.xsplit.max_len * NUFFTCT_NUM_XCD));
     const PointGeom g = p.geom();
     if (SPREAD) {
-      const int64_t sper = (p.n_sp_tasks + NUFFTCT_NUM_XCD - 1) / NUFFTCT_NUM_XCD;
-      hipLaunchKernelGGL((k_spread<T, J, TILE, CW, DEG>), dim3((unsigned)(sper * NUFFTCT_NUM_XCD)),
-                         dim3(NT), 0, st, (const cx<T>*)src, (cx<T>*)dst, (cx<double>*)p.d_partials,
-                         p.d_perm, p.d_sp_tasks, p.d_sp_segs, p.n_sp_tasks, sper, g, p.nb, P);
+      hipLaunchKernelGGL((k_spread<T, J, TILE, CW, DEG>), grd, dim3(NT_SPREAD), 0, st,
+                         (const cx<T>*)src, (cx<T>*)p.d_partials, p.d_perm, p.d_tasks, p.xsplit,
+                         g, p.nb, P);
     } else {
       hipLaunchKernelGGL((k_interp<T, J, TILE, CW, DEG>), grd, dim3(NT), 0, st,
-                         (const cx<T>*)src, (cx<T>*)dst, p.d_perm, p.d_tasks, p.ntasks, per, g,
+                         (const cx<T>*)src, (cx<T>*)dst, p.d_perm, p.d_tasks, p.xsplit, g,
                          p.nb, P);
     }
     return hipGetLastError();
@@ -367,10 +380,10 @@ hipError_t run(const nufftct_plan& p, const void* src, void* dst, hipStream_t st
 }
 
 template <typename T>
-hipError_t reduce(const nufftct_plan& p, void* grid, hipStream_t st) {
-  if (p.n_heavy == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_reduce_partials<T>), dim3((unsigned)p.n_heavy), dim3(NT), 0, st,
-                     (const cx<double>*)p.d_partials, (cx<T>*)grid, p.d_heavy, p.nb, (int)p.K, p.tile);
+hipError_t merge(const nufftct_plan& p, void* grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_merge<T>), dim3((unsigned)((int64_t)p.nb * p.nb * p.nb)), dim3(NT), 0, st,
+                     (const cx<T>*)p.d_partials, p.d_bin_tasks, (cx<T>*)grid, p.nb, (int)p.K, p.tile,
+                     p.J);
   return hipGetLastError();
 }
 
@@ -388,6 +401,6 @@ hipError_t reduce(const nufftct_plan& p, void* grid, hipStream_t st) {
     return kgrid::run<T, true>(p, in, grid, s);                                             \
   }                                                                                         \
   template <>                                                                               \
-  hipError_t launch_reduce_partials<T>(const nufftct_plan& p, void* grid, hipStream_t s) {  \
-    return kgrid::reduce<T>(p, grid, s);                                                    \
+  hipError_t launch_merge<T>(const nufftct_plan& p, void* grid, hipStream_t s) {            \
+    return kgrid::merge<T>(p, grid, s);                                                     \
   }

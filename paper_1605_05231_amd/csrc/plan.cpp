@@ -101,21 +101,16 @@ static void point_omega(const nufftct_plan& p, const std::vector<double>& geom, 
 
 struct Binning {
   std::vector<int32_t> perm;
-  std::vector<TileTask> tasks;      // interpolation
-  std::vector<SpreadSeg> segs;      // spreading
-  std::vector<SpreadTask> stasks;
-  std::vector<HeavyTile> heavy;
-  int64_t n_slots = 0;
+  std::vector<TileTask> tasks;
+  std::vector<int32_t> bin_tasks;  // nbins + 1 offsets into tasks
 };
 
-// Sort points by (bin of the first tap, spill class) and build the task lists.
-// Spill class: bit d set when the footprint first_d .. first_d + J - 1 crosses
-// into the next tile along axis d (bits ordered d0 d1 d2, d0 most significant).
+// Sort points by the tile of their first tap (stable, so each bin keeps line
+// order) and cut every bin into tasks of at most max_pts points.
 static void build_bins(const nufftct_plan& p, const std::vector<double>& geom, Binning& B) {
   const int64_t M = p.M;
   const int nb = p.nb, T = p.tile, J = p.J;
   const int64_t nbins = (int64_t)nb * nb * nb;
-  const int64_t nkeys = nbins * 8;
   std::vector<int32_t> key(M);
   const double gamma = (2.0 * M_PI) / (double)p.K;
   unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
@@ -129,29 +124,24 @@ static void build_bins(const nufftct_plan& p, const std::vector<double>& geom, B
         int first[3];
         point_omega(p, geom, i, om);
         host_first_taps(om, J, p.K, gamma, first);
-        int64_t bin = 0;
-        int cls = 0;
-        for (int d = 0; d < 3; ++d) {
-          bin = bin * nb + first[d] / T;
-          cls = cls * 2 + ((first[d] % T) + J - 1 >= T ? 1 : 0);
-        }
-        key[i] = (int32_t)(bin * 8 + cls);
+        key[i] = (int32_t)(((int64_t)(first[0] / T) * nb + first[1] / T) * nb + first[2] / T);
       }
     });
   }
   for (auto& t : th) t.join();
-  std::vector<int64_t> off(nkeys + 1, 0);
+  std::vector<int64_t> off(nbins + 1, 0);
   for (int64_t i = 0; i < M; ++i) off[key[i] + 1]++;
-  for (int64_t k = 0; k < nkeys; ++k) off[k + 1] += off[k];
+  for (int64_t k = 0; k < nbins; ++k) off[k + 1] += off[k];
   B.perm.resize(M);
   {
     std::vector<int64_t> pos(off.begin(), off.end() - 1);
     for (int64_t i = 0; i < M; ++i) B.perm[pos[key[i]]++] = (int32_t)i;
   }
-  // interpolation tasks: each bin's points in chunks of max_pts
   B.tasks.clear();
+  B.bin_tasks.assign(nbins + 1, 0);
   for (int64_t b = 0; b < nbins; ++b) {
-    const int64_t s = off[b * 8], e = off[b * 8 + 8];
+    B.bin_tasks[b] = (int32_t)B.tasks.size();
+    const int64_t s = off[b], e = off[b + 1];
     for (int64_t q = s; q < e; q += p.max_pts) {
       TileTask t;
       t.bin = (int32_t)b;
@@ -161,50 +151,7 @@ static void build_bins(const nufftct_plan& p, const std::vector<double>& geom, B
       B.tasks.push_back(t);
     }
   }
-  // spreading: per output tile, segments of the own bin and of the spilling
-  // classes of the lower neighbours; heavy tiles are split into chunks
-  B.segs.clear();
-  B.stasks.clear();
-  B.heavy.clear();
-  B.n_slots = 0;
-  for (int t0 = 0; t0 < nb; ++t0)
-    for (int t1 = 0; t1 < nb; ++t1)
-      for (int t2 = 0; t2 < nb; ++t2) {
-        const int64_t tile = ((int64_t)t0 * nb + t1) * nb + t2;
-        const int seg_begin = (int)B.segs.size();
-        int64_t work = 0;
-        for (int delta = 0; delta < 8; ++delta) {
-          const int d0 = (delta >> 2) & 1, d1 = (delta >> 1) & 1, d2 = delta & 1;
-          const int64_t sb = (((int64_t)((t0 - d0 + nb) % nb) * nb + (t1 - d1 + nb) % nb) * nb +
-                              (t2 - d2 + nb) % nb);
-          for (int c = 0; c < 8; ++c) {
-            if ((c & delta) != delta) continue;
-            const int64_t s = off[sb * 8 + c], e = off[sb * 8 + c + 1];
-            if (e == s) continue;
-            if (!B.segs.empty() && (int)B.segs.size() > seg_begin &&
-                B.segs.back().delta == delta &&
-                B.segs.back().start + B.segs.back().count == s) {
-              B.segs.back().count += (int32_t)(e - s);  // adjacent classes merge
-            } else {
-              B.segs.push_back({(int32_t)s, (int32_t)(e - s), delta, 0});
-            }
-            work += e - s;
-          }
-        }
-        const int seg_end = (int)B.segs.size();
-        if (work <= p.max_pts) {
-          B.stasks.push_back({(int32_t)tile, seg_begin, seg_end, 0, (int32_t)work, -1, 0, 0});
-        } else {
-          const int64_t nch = (work + p.max_pts - 1) / p.max_pts;
-          B.heavy.push_back({(int32_t)tile, (int32_t)B.n_slots, (int32_t)(B.n_slots + nch), 0});
-          for (int64_t c = 0; c < nch; ++c) {
-            const int64_t lo = c * work / nch, hi = (c + 1) * work / nch;
-            B.stasks.push_back({(int32_t)tile, seg_begin, seg_end, (int32_t)lo, (int32_t)hi,
-                                (int32_t)(B.n_slots + c), 0, 0});
-          }
-          B.n_slots += nch;
-        }
-      }
+  B.bin_tasks[nbins] = (int32_t)B.tasks.size();
 }
 
 // ---------------------------------------------------------------------------
@@ -217,9 +164,7 @@ static void free_plan(nufftct_plan* p) {
   hipFree(p->d_tw_r);
   hipFree(p->d_perm);
   hipFree(p->d_tasks);
-  hipFree(p->d_sp_segs);
-  hipFree(p->d_sp_tasks);
-  hipFree(p->d_heavy);
+  hipFree(p->d_bin_tasks);
   hipFree(p->d_partials);
   hipFree(p->d_grid);
   hipFree(p->d_tmp);
@@ -289,15 +234,14 @@ static int create(nufftct_plan** out, int64_t N, int64_t K, int J, int kernel, d
   p->n_r = n_r;
   p->radial = radial;
   p->n_lines = radial ? n_geom : (n_r ? M / n_r : 0);
-  // tile edge: divides K, covers a footprint's spill (J - 1 <= tile), and the
-  // interpolation's staged tile plus halo fits in LDS
+  // tile edge: divides K, J - 1 <= tile, and the spread's FP64 halo tile of
+  // (tile + J - 1)^3 cells fits in LDS
   {
-    const int cxb = precision == NUFFTCT_FP32 ? 8 : 16;
-    auto halo_bytes = [&](int t) { return (t + J - 1) * (t + J - 1) * (t + J - 1) * cxb; };
+    auto halo_bytes = [&](int t) { return (t + J - 1) * (t + J - 1) * (t + J - 1) * 16; };
     int t = env_int("NUFFTCT_TILE", precision == NUFFTCT_FP32 ? 16 : 8);
     if (t != 8 && t != 16) t = 16;
-    if (t == 16 && (K % 16 || halo_bytes(16) > 96 * 1024)) t = 8;
-    if (K % t || J - 1 > t || halo_bytes(t) > 96 * 1024) {
+    if (t == 16 && (K % 16 || halo_bytes(16) > 160 * 1024)) t = 8;
+    if (K % t || J - 1 > t || halo_bytes(t) > 160 * 1024) {
       free_plan(p);
       return fail(NUFFTCT_EINVAL, "no tile edge fits K=%lld, J=%d", (long long)K, J);
     }
@@ -374,21 +318,37 @@ static int create(nufftct_plan** out, int64_t N, int64_t K, int J, int kernel, d
     Binning B;
     build_bins(*p, g, B);
     p->ntasks = (int64_t)B.tasks.size();
-    p->n_sp_tasks = (int64_t)B.stasks.size();
-    p->n_heavy = (int64_t)B.heavy.size();
-    p->n_slots = B.n_slots;
+    {
+      // cut the task list into NUFFTCT_NUM_XCD contiguous ranges of equal point count
+      int64_t total = 0;
+      for (const auto& t : B.tasks) total += t.count;
+      int64_t acc = 0;
+      size_t i = 0;
+      p->xsplit.start[0] = 0;
+      for (int x = 1; x < NUFFTCT_NUM_XCD; ++x) {
+        const int64_t target = total * x / NUFFTCT_NUM_XCD;
+        while (i < B.tasks.size() && acc + B.tasks[i].count / 2 < target) acc += B.tasks[i++].count;
+        p->xsplit.start[x] = (int32_t)i;
+      }
+      p->xsplit.start[NUFFTCT_NUM_XCD] = (int32_t)B.tasks.size();
+      p->xsplit.max_len = 0;
+      for (int x = 0; x < NUFFTCT_NUM_XCD; ++x)
+        p->xsplit.max_len = std::max(p->xsplit.max_len, p->xsplit.start[x + 1] - p->xsplit.start[x]);
+      p->xsplit.max_len = std::max(p->xsplit.max_len, 1);
+    }
     if ((rc = upload((void**)&p->d_perm, B.perm.data(), B.perm.size(), st))) return bail(rc);
     if ((rc = upload((void**)&p->d_tasks, B.tasks.data(), B.tasks.size(), st))) return bail(rc);
-    if ((rc = upload((void**)&p->d_sp_segs, B.segs.data(), B.segs.size(), st))) return bail(rc);
-    if ((rc = upload((void**)&p->d_sp_tasks, B.stasks.data(), B.stasks.size(), st))) return bail(rc);
-    if ((rc = upload((void**)&p->d_heavy, B.heavy.data(), B.heavy.size(), st))) return bail(rc);
-    // partial tiles hold FP64 accumulators in both precisions
-    const size_t pbytes = (size_t)std::max<int64_t>(p->n_slots, 1) * p->tile * p->tile * p->tile * 16;
+    if ((rc = upload((void**)&p->d_bin_tasks, B.bin_tasks.data(), B.bin_tasks.size(), st)))
+      return bail(rc);
+    const size_t cxb = precision == NUFFTCT_FP32 ? 8 : 16;
+    const size_t S = (size_t)(p->tile + J - 1);
+    const size_t pbytes = (size_t)std::max<int64_t>(p->ntasks, 1) * S * S * S * cxb;
     hipError_t e = hipMalloc(&p->d_partials, pbytes);
     if (e != hipSuccess) {
       free_plan(p);
-      return fail(NUFFTCT_ENOMEM, "partial tiles of %zu bytes: %s", pbytes, hipGetErrorString(e));
+      return fail(NUFFTCT_ENOMEM, "spread partial tiles of %zu bytes: %s", pbytes, hipGetErrorString(e));
     }
+    p->partial_bytes = pbytes;
     // host vectors go out of scope after the copies complete
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
@@ -467,12 +427,12 @@ static hipError_t run_stage(nufftct_plan* p, int stage, const void* in, void* ou
       e = launch_radial<T>(*p, in, out, true, (flags & NUFFTCT_DERIV) != 0, st);
       break;
     case NUFFTCT_STAGE_SPREAD: {
-      // every grid cell is written (no clearing); split tiles are then reduced,
-      // timed on their own slot
+      // halo partials per task, then the owner-computes merge writes every
+      // grid cell (timed on its own slot)
       e = launch_spread<T>(*p, in, out, st);
       tm.done();
-      StageTimer tr(p, st, NUFFTCT_TIMING_REDUCE);
-      if (e == hipSuccess) e = launch_reduce_partials<T>(*p, out, st);
+      StageTimer tr(p, st, NUFFTCT_TIMING_MERGE);
+      if (e == hipSuccess) e = launch_merge<T>(*p, out, st);
       tr.done();
       break;
     }
@@ -608,7 +568,7 @@ int nufftct_plan_info(const nufftct_plan* p, int64_t* N, int64_t* K, int* J, int
   if (M) *M = p->M;
   if (n_r) *n_r = p->n_r;
   if (precision) *precision = p->precision;
-  if (workspace_bytes) *workspace_bytes = (int64_t)(p->grid_bytes + p->tmp_bytes);
+  if (workspace_bytes) *workspace_bytes = (int64_t)(p->grid_bytes + p->tmp_bytes + p->partial_bytes);
   return NUFFTCT_OK;
 }
 

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/nufftct.h"
+#include "cx.h"
 
 // Degree of the per-tap weight polynomials (piecewise Horner form of the
 // interpolation kernel on each unit interval), per precision.
@@ -40,35 +41,6 @@ struct TileTask {
   int32_t pad;
 };
 
-// Spreading is owner-computes: every output tile is produced by the task(s)
-// that own it.  A tile's points are those of its own bin plus those of the 7
-// lower-neighbour bins whose footprints spill into it; each such group is a
-// contiguous segment of the permutation (points are sorted by bin, then by
-// spill class).
-struct SpreadSeg {
-  int32_t start;  // first entry in the permutation
-  int32_t count;
-  int32_t delta;  // source bin = tile - (d0, d1, d2), packed d0*4 + d1*2 + d2
-  int32_t pad;
-};
-
-struct SpreadTask {
-  int32_t tile;       // linear output tile index
-  int32_t seg_begin;  // segments [seg_begin, seg_end)
-  int32_t seg_end;
-  int32_t p_lo;       // sub-range of the tile's concatenated segment points
-  int32_t p_hi;
-  int32_t slot;       // -1: write the grid directly; else partial-tile slot
-  int32_t pad0, pad1;
-};
-
-struct HeavyTile {
-  int32_t tile;
-  int32_t slot_begin;  // partial tiles [slot_begin, slot_end) summed in order
-  int32_t slot_end;
-  int32_t pad;
-};
-
 struct nufftct_plan {
   int64_t N = 0, K = 0, M = 0, n_r = 0, n_lines = 0;
   int J = 0, kernel = 0, precision = 0;
@@ -86,17 +58,15 @@ struct nufftct_plan {
   double* d_s = nullptr;        // deapodization s(m), N doubles
   void* d_tw_K = nullptr;       // twiddles for length K (plan precision)
   void* d_tw_r = nullptr;       // twiddles for length n_r
-  int32_t* d_perm = nullptr;    // M point ids sorted by tile, then spill class
-  TileTask* d_tasks = nullptr;  // interpolation tasks (bin, <= max_pts points)
+  int32_t* d_perm = nullptr;       // M point ids sorted by tile
+  TileTask* d_tasks = nullptr;     // tasks: a bin and <= max_pts of its points
   int64_t ntasks = 0;
-  SpreadSeg* d_sp_segs = nullptr;
-  SpreadTask* d_sp_tasks = nullptr;
-  HeavyTile* d_heavy = nullptr;
-  void* d_partials = nullptr;   // partial tiles of split output tiles
-  int64_t n_sp_tasks = 0, n_heavy = 0, n_slots = 0;
+  XcdSplit xsplit{};               // per-XCD task ranges of equal point count
+  int32_t* d_bin_tasks = nullptr;  // nb^3 + 1 offsets: tasks of bin b are [o[b], o[b+1])
+  void* d_partials = nullptr;      // per task, its spread halo tile (S^3 complex)
   void* d_grid = nullptr;       // K^3 complex workspace
   void* d_tmp = nullptr;        // M complex workspace
-  size_t grid_bytes = 0, tmp_bytes = 0;
+  size_t grid_bytes = 0, tmp_bytes = 0, partial_bytes = 0;
 
   // weight polynomials (host copies passed by value to kernels)
   WeightPoly<float, NUFFTCT_DEG_F32> wp32;
@@ -137,7 +107,7 @@ template <typename T>
 hipError_t launch_spread(const nufftct_plan& p, const void* in, void* grid, hipStream_t s);
 hipError_t launch_zero(void* ptr, size_t bytes, hipStream_t s);
 template <typename T>
-hipError_t launch_reduce_partials(const nufftct_plan& p, void* grid, hipStream_t s);
+hipError_t launch_merge(const nufftct_plan& p, void* grid, hipStream_t s);
 
 bool fft_length_supported(int64_t L);
 // record this thread's error message (read back by nufftct_last_error); returns code

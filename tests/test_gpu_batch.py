@@ -1,0 +1,97 @@
+"""Uneven batches (the c5 workload: 64 volumes, N in {48..160}, K = 2N, J = 6,
+own direction sets with N_phi in [60, 240], N_theta = N_phi/2, N_r = 2N) and
+HIP-graph replay."""
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import nufft, projector
+from tests.gpu_util import rel_l2, require_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _make(items):
+    import torch
+    import paper_1605_05231_amd as pkg
+    dirs = [w.directions() for w in items]
+    b = pkg.Batch([w.N for w in items], [w.K for w in items], 6, dirs, [w.n_r for w in items])
+    xs = [torch.from_numpy(w.volume().astype(np.complex64)).cuda() for w in items]
+    outs = [torch.empty(w.M, dtype=torch.complex64, device="cuda") for w in items]
+    vols = [torch.empty(w.N ** 3, dtype=torch.complex64, device="cuda") for w in items]
+    return b, dirs, xs, outs, vols
+
+
+def test_small_uneven_batch_vs_oracle():
+    require_gpu()
+    items = [synthetic.Workload(f"b{i}", N=n, K=2 * n, J=6, n_phi=p, n_theta=p // 2, n_r=2 * n,
+                                n_ell=10 + i, seed=5000 + i)
+             for i, (n, p) in enumerate([(48, 12), (64, 8), (48, 10), (32, 16)])]
+    b, dirs, xs, outs, vols = _make(items)
+    b.forward(xs, outs)
+    b.adjoint(outs, vols)
+    for i, w in enumerate(items):
+        prm = nufft.Params(w.N, w.K, 6)
+        x = xs[i].cpu().numpy().astype(complex)
+        want = projector.forward(x, dirs[i], w.n_r, prm)
+        got = outs[i].cpu().numpy()
+        ef = rel_l2(got, want)
+        wa = projector.adjoint(got.astype(complex), dirs[i], w.n_r, prm)
+        ea = rel_l2(vols[i].cpu().numpy(), wa.reshape(-1))
+        say(f"batch item {i} N={w.N} fwd={ef:.2e} adj={ea:.2e}")
+        assert ef < 1e-5 and ea < 1e-5
+
+
+def test_c5_batch_graph_replay():
+    """The full 64-volume c5 batch: batched results equal single-plan results
+    bit for bit, and graph replays equal the eager run bit for bit on every
+    replay (eager work and synchronisations between replays)."""
+    require_gpu()
+    import torch
+    import paper_1605_05231_amd as pkg
+    items = synthetic.batch_workload(64)
+    say(f"c5 total points {sum(w.M for w in items)}")
+    b, dirs, xs, outs, vols = _make(items)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b.forward(xs, outs)
+        b.adjoint(outs, vols)
+    stream.synchronize()
+    ref_out = [o.clone() for o in outs]
+    ref_vol = [v.clone() for v in vols]
+    # spot-check four members against independent single plans
+    for i in (0, 17, 40, 63):
+        w = items[i]
+        p = pkg.Plan(w.N, w.K, 6, dirs=dirs[i], n_r=w.n_r)
+        o = p.forward(xs[i])
+        assert torch.equal(o.reshape(-1), ref_out[i])
+        assert torch.equal(p.adjoint(o).reshape(-1), ref_vol[i])
+    # graph capture of forward and adjoint; replays vs eager results
+    with torch.cuda.stream(stream):
+        b.capture(0, xs, outs, stream=stream)
+        b.capture(1, outs, vols, stream=stream)
+    for rep in range(3):
+        for o in outs:
+            o.zero_()
+        for v in vols:
+            v.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            b.replay(0, stream=stream)
+            b.replay(1, stream=stream)
+        stream.synchronize()
+        # unrelated eager work between replays
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        for i in range(len(items)):
+            assert torch.equal(outs[i], ref_out[i]), (rep, i)
+            assert torch.equal(vols[i], ref_vol[i]), (rep, i)
+    # the small members against the oracle
+    for i, w in enumerate(items):
+        if w.N == 48 and w.n_phi <= 80:
+            prm = nufft.Params(w.N, w.K, 6)
+            x = xs[i].cpu().numpy().astype(complex)
+            e = rel_l2(ref_out[i].cpu().numpy(), projector.forward(x, dirs[i], w.n_r, prm))
+            say(f"c5 item {i} vs oracle {e:.2e}")
+            assert e < 1e-5
+            break
