@@ -199,7 +199,10 @@ __global__ __launch_bounds__(NT_SPREAD) void k_spread(const cx<T>* __restrict__ 
   constexpr bool FIXED = sizeof(T) == 4;
   constexpr int S = TILE + J - 1;
   constexpr int SS = S * S * S;
-  __shared__ cx<double> acc[SS];  // FP64 sums, or (re, im) int64 pairs on the FP32 path
+  // planar accumulators (all real parts, then all imaginary parts): a wave's
+  // 64-bit atomics then spread over every LDS bank instead of half of them.
+  // FP64 sums, or int64 sums on the FP32 path.
+  __shared__ double acc[2 * SS];
   __shared__ unsigned int s_maxbits;
   long long* acci = reinterpret_cast<long long*>(acc);
   const int64_t task_id = xcd_task(blockIdx.x, xs);
@@ -207,7 +210,7 @@ __global__ __launch_bounds__(NT_SPREAD) void k_spread(const cx<T>* __restrict__ 
   const TileTask tk = tasks[task_id];
   const int b2 = tk.bin % nb, b1 = (tk.bin / nb) % nb, b0 = tk.bin / (nb * nb);
   const int o0 = b0 * TILE, o1 = b1 * TILE, o2 = b2 * TILE;
-  for (int idx = threadIdx.x; idx < SS; idx += NT_SPREAD) acc[idx] = cx<double>{0, 0};
+  for (int idx = threadIdx.x; idx < 2 * SS; idx += NT_SPREAD) acc[idx] = 0.0;
   T scale = (T)1;
   if constexpr (FIXED) {
     if (threadIdx.x == 0) s_maxbits = 0u;
@@ -256,11 +259,11 @@ __global__ __launch_bounds__(NT_SPREAD) void k_spread(const cx<T>* __restrict__ 
           const cx<T> u =
               CW ? cmulc(vb, cx<T>{w2r[c], w2i[c]}) : cx<T>{w2r[c] * vb.x, w2r[c] * vb.y};
           if constexpr (FIXED) {
-            lds_add(&acci[2 * (row + c)], (long long)__float2int_rn(u.x));
-            lds_add(&acci[2 * (row + c) + 1], (long long)__float2int_rn(u.y));
+            lds_add(&acci[row + c], (long long)__float2int_rn(u.x));
+            lds_add(&acci[SS + row + c], (long long)__float2int_rn(u.y));
           } else {
-            lds_add(&acc[row + c].x, (double)u.x);
-            lds_add(&acc[row + c].y, (double)u.y);
+            lds_add(&acc[row + c], (double)u.x);
+            lds_add(&acc[SS + row + c], (double)u.y);
           }
         }
       }
@@ -271,41 +274,42 @@ __global__ __launch_bounds__(NT_SPREAD) void k_spread(const cx<T>* __restrict__ 
   if constexpr (FIXED) {
     const double inv = 1.0 / (double)scale;
     for (int idx = threadIdx.x; idx < SS; idx += NT_SPREAD)
-      dst[idx] = cx<T>{(T)((double)acci[2 * idx] * inv), (T)((double)acci[2 * idx + 1] * inv)};
+      dst[idx] = cx<T>{(T)((double)acci[idx] * inv), (T)((double)acci[SS + idx] * inv)};
   } else {
-    for (int idx = threadIdx.x; idx < SS; idx += NT_SPREAD)
-      dst[idx] = cx<T>{(T)acc[idx].x, (T)acc[idx].y};
+    for (int idx = threadIdx.x; idx < SS; idx += NT_SPREAD) dst[idx] = cx<T>{(T)acc[idx], (T)acc[SS + idx]};
   }
 }
 
-// Spreading, phase 2 (owner computes): one workgroup per output tile sums, for
-// each of its cells, the halo partials that cover it -- those of every task of
-// its own bin and of the 7 lower-neighbour bins (their halos reach J-1 cells
-// into this tile) -- in a fixed order, and writes every cell of the grid once.
-template <typename T>
+// Spreading, phase 2 (owner computes): each grid cell is the fixed-order sum
+// of the halo partials that cover it -- those of every task of its own bin and
+// of the lower-neighbour bins whose halos reach it (J-1 cells into the tile).
+// One thread per cell, TILE^3 / NT blocks per tile: the cells' independent
+// loads give the memory system enough requests in flight.
+template <typename T, int TILE>
 __global__ __launch_bounds__(NT) void k_merge(const cx<T>* __restrict__ partials,
                                               const int32_t* __restrict__ bin_tasks,
-                                              cx<T>* __restrict__ grid, int nb, int K, int TILE,
-                                              int J) {
-  const int S = TILE + J - 1;
+                                              cx<T>* __restrict__ grid, int nb, int K, int S) {
+  constexpr int TT = TILE * TILE * TILE;
+  constexpr int BPT = TT / NT;  // blocks per tile
+  static_assert(TT % NT == 0, "tile cells must be a multiple of the block size");
   const int64_t SS = (int64_t)S * S * S;
-  const int tile = blockIdx.x;
+  const int tile = (int)(blockIdx.x / BPT);
+  const int idx = (int)(blockIdx.x % BPT) * NT + (int)threadIdx.x;
   const int t2 = tile % nb, t1 = (tile / nb) % nb, t0 = tile / (nb * nb);
-  const int TT = TILE * TILE * TILE;
-  for (int idx = threadIdx.x; idx < TT; idx += NT) {
-    const int i2 = idx % TILE, i1 = (idx / TILE) % TILE, i0 = idx / (TILE * TILE);
-    cx<T> sum = {0, 0};
-    for (int delta = 0; delta < 8; ++delta) {
-      const int d0 = (delta >> 2) & 1, d1 = (delta >> 1) & 1, d2 = delta & 1;
-      // position of this cell inside the halo of bin (tile - delta)
-      const int q0 = i0 + d0 * TILE, q1 = i1 + d1 * TILE, q2 = i2 + d2 * TILE;
-      if (q0 >= S || q1 >= S || q2 >= S) continue;
+  const int i2 = idx % TILE, i1 = (idx / TILE) % TILE, i0 = idx / (TILE * TILE);
+  cx<T> acc = {0, 0};
+#pragma unroll
+  for (int delta = 0; delta < 8; ++delta) {
+    const int d0 = (delta >> 2) & 1, d1 = (delta >> 1) & 1, d2 = delta & 1;
+    // position of this cell inside the halo of bin (tile - delta)
+    const int q0 = i0 + d0 * TILE, q1 = i1 + d1 * TILE, q2 = i2 + d2 * TILE;
+    if (q0 < S && q1 < S && q2 < S) {
       const int sb = (((t0 - d0 + nb) % nb) * nb + (t1 - d1 + nb) % nb) * nb + (t2 - d2 + nb) % nb;
       const int64_t off = ((int64_t)q0 * S + q1) * S + q2;
-      for (int t = bin_tasks[sb]; t < bin_tasks[sb + 1]; ++t) sum = cadd(sum, partials[t * SS + off]);
+      for (int t = bin_tasks[sb]; t < bin_tasks[sb + 1]; ++t) acc = cadd(acc, partials[t * SS + off]);
     }
-    grid[((int64_t)(t0 * TILE + i0) * K + (t1 * TILE + i1)) * K + (t2 * TILE + i2)] = sum;
   }
+  grid[((int64_t)(t0 * TILE + i0) * K + (t1 * TILE + i1)) * K + (t2 * TILE + i2)] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -381,9 +385,16 @@ hipError_t run(const nufftct_plan& p, const void* src, void* dst, hipStream_t st
 
 template <typename T>
 hipError_t merge(const nufftct_plan& p, void* grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_merge<T>), dim3((unsigned)((int64_t)p.nb * p.nb * p.nb)), dim3(NT), 0, st,
-                     (const cx<T>*)p.d_partials, p.d_bin_tasks, (cx<T>*)grid, p.nb, (int)p.K, p.tile,
-                     p.J);
+  const int S = p.tile + p.J - 1;
+  const dim3 grd((unsigned)((int64_t)p.nb * p.nb * p.nb * p.tile * p.tile * p.tile / NT));
+  if (p.tile == 16)
+    hipLaunchKernelGGL((k_merge<T, 16>), grd, dim3(NT), 0, st, (const cx<T>*)p.d_partials,
+                       p.d_bin_tasks, (cx<T>*)grid, p.nb, (int)p.K, S);
+  else if (p.tile == 8)
+    hipLaunchKernelGGL((k_merge<T, 8>), grd, dim3(NT), 0, st, (const cx<T>*)p.d_partials,
+                       p.d_bin_tasks, (cx<T>*)grid, p.nb, (int)p.K, S);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -105,30 +105,39 @@ struct Binning {
   std::vector<int32_t> bin_tasks;  // nbins + 1 offsets into tasks
 };
 
-// Sort points by the tile of their first tap (stable, so each bin keeps line
-// order) and cut every bin into tasks of at most max_pts points.
+// Sort points by the tile of their first tap and cut every bin into tasks of
+// at most max_pts points.  Within a task the points are then interleaved by
+// the LDS bank of their first tap's cell in the staged halo tile: with cell
+// c = (l0 S + l1) S + l2 (S = tile + J - 1), points are dealt round-robin over
+// the residues c mod 32, so the 32 lanes of a half-wave start on distinct
+// 8-byte bank pairs and a tap offset shared by all lanes keeps them distinct.
 static void build_bins(const nufftct_plan& p, const std::vector<double>& geom, Binning& B) {
   const int64_t M = p.M;
   const int nb = p.nb, T = p.tile, J = p.J;
+  const int S = T + J - 1;
   const int64_t nbins = (int64_t)nb * nb * nb;
   std::vector<int32_t> key(M);
+  std::vector<uint8_t> res(M);
   const double gamma = (2.0 * M_PI) / (double)p.K;
   unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   if (M < 200000) nth = 1;
-  std::vector<std::thread> th;
-  for (unsigned t = 0; t < nth; ++t) {
-    th.emplace_back([&, t]() {
-      const int64_t a = M * t / nth, b = M * (t + 1) / nth;
-      for (int64_t i = a; i < b; ++i) {
-        double om[3];
-        int first[3];
-        point_omega(p, geom, i, om);
-        host_first_taps(om, J, p.K, gamma, first);
-        key[i] = (int32_t)(((int64_t)(first[0] / T) * nb + first[1] / T) * nb + first[2] / T);
-      }
-    });
-  }
-  for (auto& t : th) t.join();
+  auto parallel = [&](int64_t n, auto&& fn) {
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nth; ++t)
+      th.emplace_back([&, t]() { fn(n * t / nth, n * (t + 1) / nth); });
+    for (auto& t : th) t.join();
+  };
+  parallel(M, [&](int64_t a, int64_t b) {
+    for (int64_t i = a; i < b; ++i) {
+      double om[3];
+      int first[3];
+      point_omega(p, geom, i, om);
+      host_first_taps(om, J, p.K, gamma, first);
+      key[i] = (int32_t)(((int64_t)(first[0] / T) * nb + first[1] / T) * nb + first[2] / T);
+      const int c = ((first[0] % T) * S + first[1] % T) * S + first[2] % T;
+      res[i] = (uint8_t)(c & 31);
+    }
+  });
   std::vector<int64_t> off(nbins + 1, 0);
   for (int64_t i = 0; i < M; ++i) off[key[i] + 1]++;
   for (int64_t k = 0; k < nbins; ++k) off[k + 1] += off[k];
@@ -152,6 +161,26 @@ static void build_bins(const nufftct_plan& p, const std::vector<double>& geom, B
     }
   }
   B.bin_tasks[nbins] = (int32_t)B.tasks.size();
+  // deal each task's points round-robin over the 32 bank residues
+  parallel((int64_t)B.tasks.size(), [&](int64_t a, int64_t b) {
+    std::vector<int32_t> tmp;
+    std::vector<int32_t> cnt(33);
+    for (int64_t k = a; k < b; ++k) {
+      const TileTask& t = B.tasks[k];
+      int32_t* pts = B.perm.data() + t.start;
+      std::fill(cnt.begin(), cnt.end(), 0);
+      for (int i = 0; i < t.count; ++i) cnt[res[pts[i]] + 1]++;
+      for (int r = 0; r < 32; ++r) cnt[r + 1] += cnt[r];
+      tmp.assign(pts, pts + t.count);
+      std::vector<int32_t> bucket(t.count);
+      std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+      for (int i = 0; i < t.count; ++i) bucket[fill[res[tmp[i]]]++] = tmp[i];
+      int o = 0;
+      for (int round = 0; o < t.count; ++round)
+        for (int r = 0; r < 32; ++r)
+          if (cnt[r] + round < cnt[r + 1]) pts[o++] = bucket[cnt[r] + round];
+    }
+  });
 }
 
 // ---------------------------------------------------------------------------
