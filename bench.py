@@ -49,6 +49,94 @@ def alg_bytes(N, K, M, cb, touched):
     }
 
 
+# ---------------------------------------------------------------------------
+# rocprofv3 post-processing (summaries committed under profiles/)
+KERNEL_SOURCES = {"interp": "k_grid_impl.h", "spread": "k_grid_impl.h", "merge": "k_grid_impl.h",
+                  "radial": "k_fft_impl.h", "radial_adj": "k_fft_impl.h"}
+KERNEL_NAMES = {"interp": "k_interp", "spread": "k_spread", "merge": "k_merge",
+                "radial": "k_radial<float, 512, false>", "radial_adj": "k_radial<float, 512, true>"}
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "hbm_traffic_c3.json")
+
+
+def source_sha(fname):
+    import hashlib
+    path = os.path.join(ROOT, "paper_1605_05231_amd", "csrc", fname)
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def _short(name):
+    import re
+    n = name.replace("void ", "")
+    return (re.sub(r"\(.*$", "", n) if not n.startswith("at::") else n[:60])[:80]
+
+
+def summarize_stats(csv_path):
+    import csv
+    print(f"{'kernel':80s} {'calls':>5s} {'avg_us':>10s} {'total_ms':>9s} {'pct':>6s}")
+    for r in csv.DictReader(open(csv_path)):
+        print(f"{_short(r['Name']):80s} {int(r['Calls']):5d} {float(r['AverageNs']) / 1e3:10.1f} "
+              f"{float(r['TotalDurationNs']) / 1e6:9.2f} {float(r['Percentage']):6.2f}")
+
+
+def summarize_counters(fetch_csv, write_csv):
+    """Mean FETCH_SIZE / WRITE_SIZE (KiB per dispatch) per kernel, the copy-kernel
+    scale factors (1 GiB read and written by one plain copy), and the scaled
+    HBM traffic per launch; writes the traffic record used by the benchmark."""
+    import collections
+    import csv
+    vals = {}
+    for cname, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        agg = collections.OrderedDict()
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == cname:
+                agg.setdefault(_short(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+        vals[cname] = {k: sum(v) / len(v) for k, v in agg.items()}
+    gib_kib = 1024.0 * 1024.0
+    # the 1 GiB copies: the dispatch whose WRITE_SIZE is closest to 1 GiB, per copy kernel
+    cands = {}
+    for cname, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        for r in csv.DictReader(open(path)):
+            k = _short(r["Kernel_Name"])
+            if r["Counter_Name"] == cname and ("copyBuffer" in k or "manual_unroll<128, 4" in k):
+                cands.setdefault((k, r["Dispatch_Id"]), {})[cname] = float(r["Counter_Value"])
+    best = {}
+    for (k, d), v in cands.items():
+        if "WRITE_SIZE" in v and abs(v["WRITE_SIZE"] - gib_kib) < 0.05 * gib_kib:
+            best[k] = v
+    for k, v in best.items():
+        print(f"# copy kernel {k}: FETCH {v.get('FETCH_SIZE', float('nan')):.1f} KiB, "
+              f"WRITE {v['WRITE_SIZE']:.1f} KiB for 1 GiB read + 1 GiB written")
+    ck = sorted(best)[0]
+    f_fetch = gib_kib / best[ck]["FETCH_SIZE"]
+    f_write = gib_kib / best[ck]["WRITE_SIZE"]
+    print(f"# scale factors from {ck}: f_fetch {f_fetch:.3f}, f_write {f_write:.3f}")
+    print(f"{'kernel':80s} {'FETCH_KiB':>12s} {'WRITE_KiB':>12s} {'scaled_GB':>10s}")
+    rec = {"f_fetch": f_fetch, "f_write": f_write, "kernels": {}}
+    for k in vals["FETCH_SIZE"]:
+        fe, wr = vals["FETCH_SIZE"][k], vals["WRITE_SIZE"].get(k, float("nan"))
+        gb = (fe * f_fetch + wr * f_write) * 1024 / 1e9
+        print(f"{k:80s} {fe:12.1f} {wr:12.1f} {gb:10.4f}")
+        for stage, kn in KERNEL_NAMES.items():
+            if kn in k and "float" in k:
+                rec["kernels"][stage] = {"fetch_kib": fe, "write_kib": wr, "traffic_bytes": gb * 1e9,
+                                         "source": KERNEL_SOURCES[stage],
+                                         "source_sha": source_sha(KERNEL_SOURCES[stage])}
+    with open(TRAFFIC_JSON, "w") as f:
+        json.dump(rec, f, indent=1)
+
+
+def traffic_for(stage):
+    """Scaled HBM bytes per launch of `stage` if the committed counters were
+    taken on the current kernel source, else None."""
+    try:
+        rec = json.load(open(TRAFFIC_JSON))["kernels"][stage]
+    except (OSError, KeyError, ValueError):
+        return None
+    if rec.get("source_sha") != source_sha(rec["source"]):
+        return None
+    return rec["traffic_bytes"]
+
+
 def cpu_oracle_baseline(x, dirs, n_r, N, K, J, sample_lines):
     """Time the CPU FP64 oracle on the full grid with a sample of the lines.
 
@@ -92,11 +180,23 @@ def main():
     ap.add_argument("--workload", default="c3", choices=["c2", "c3"])
     ap.add_argument("--kernel", default="kb", choices=["kb", "minmax"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the tiling autotuner (defaults: tile 16, 4096 points per task)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-form comparison")
     ap.add_argument("--cpu-sample-lines", type=int, default=640)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (reference for HBM counters)")
+    ap.add_argument("--summarize-stats", metavar="KERNEL_STATS_CSV",
+                    help="print a summary of a rocprofv3 --stats kernel table and exit")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="summarize two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) and exit")
     args = ap.parse_args()
+    if args.summarize_stats:
+        summarize_stats(args.summarize_stats)
+        return
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters)
+        return
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the projector runs "
@@ -120,6 +220,11 @@ def main():
     x_np = W.volume()
     log(f"[bench] phantom {time.perf_counter() - t0:.1f}s")
 
+    tune = None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        tune = pkg.autotune(N, K, J, dirs, n_r, kernel=args.kernel)
+        log(f"[bench] autotune {tune} in {time.perf_counter() - t0:.1f}s")
     t0 = time.perf_counter()
     plan = pkg.Plan(N, K, J, dirs=dirs, n_r=n_r, kernel=args.kernel, dtype=torch.complex64)
     torch.cuda.synchronize()
@@ -127,12 +232,20 @@ def main():
     log(f"[bench] plan {plan_s:.2f}s")
 
     if args.copy_calibration:
+        import ctypes
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)  # torch's elementwise copy kernel
+        torch.cuda.synchronize()
+        hip = ctypes.CDLL("libamdhip64.so")
+        hip.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                       ctypes.c_int, ctypes.c_void_p]
+        rc = hip.hipMemcpyAsync(dst.data_ptr(), src.data_ptr(), 1 << 30, 3,  # device to device
+                                ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
         torch.cuda.synchronize()
         del src, dst
-        log("[bench] copy calibration: 1 GiB read + 1 GiB written by one copy kernel")
+        log(f"[bench] copy calibration: two 1 GiB device copies (torch kernel, hipMemcpyAsync rc={rc})")
 
     x = torch.from_numpy(x_np.astype(np.complex64)).cuda()
     D = torch.empty((len(dirs), n_r), dtype=torch.complex64, device="cuda")
@@ -171,8 +284,10 @@ def main():
     single = ["interp", "spread", "merge", "radial", "radial_adj"]
     dom = max(single, key=lambda k: stage_avg[k])
     achieved = ab[dom] / (stage_avg[dom] * 1e-3) / 1e9
+    tr = traffic_for(dom)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if tr is None else round(tr),
                 "alg_bytes_per_launch": ab[dom], "avg_launch_ms": round(stage_avg[dom], 4)}
     stages = {k: {"avg_ms": round(stage_avg[k], 4),
                   "alg_GBps": round(ab[k] / (stage_avg[k] * 1e-3) / 1e9, 1) if stage_avg[k] and ab[k] else None}
@@ -191,6 +306,7 @@ def main():
         "stages": stages,
         "touched_cells": touched,
         "plan_s": round(plan_s, 2),
+        "tiling": tune or "default",
     }
 
     # FP64 form: speed and the FP32 path's error against it

@@ -122,6 +122,22 @@ int nufftct_plan_create_radial(nufftct_plan** out, int64_t N, int64_t K, int J, 
                                int64_t n_lines, int64_t n_r, void* stream);
 
 /*
+ * Autotune the tiling of radial plans with these parameters: builds candidate
+ * plans (tile edge 16 or 8 cells x 1024..8192 points per task), times one
+ * forward + adjoint (flags as for nufftct_forward) of each on `stream`, and
+ * records the fastest in a process-wide table that every later plan creation
+ * with the same (N, K, J, kernel, precision, n_lines, n_r) uses.  With the
+ * environment variable NUFFTCT_TUNE_CACHE naming a file, results are appended
+ * there and read back by later processes.  NUFFTCT_TILE / NUFFTCT_MAXPTS in the
+ * environment override the table.  Blocking; allocates temporary buffers.
+ * Outputs (any may be NULL): the chosen tile edge, points per task and the
+ * measured milliseconds per forward + adjoint.
+ */
+int nufftct_autotune_radial(int64_t N, int64_t K, int J, int kernel, double beta, int precision,
+                            const double* dirs, int64_t n_lines, int64_t n_r, int flags,
+                            int* best_tile, int* best_max_pts, double* best_ms, void* stream);
+
+/*
  * Forward operator: vol (device, N^3 complex) -> out (device, M complex, line
  * order p = l*n_r + c).  flags: 0 = plain NUFFT values X^(omega_p);
  * NUFFTCT_RADIAL adds the radial inverse DFT; NUFFTCT_DERIV_RADIAL adds the

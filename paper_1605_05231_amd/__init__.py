@@ -17,7 +17,7 @@ from ._lib import (DERIV, DERIV_RADIAL, FP32, FP64, KERNEL_KB, KERNEL_MINMAX_KB,
                    STAGE_IFFT_CROP, STAGE_INTERP, STAGE_NAMES, STAGE_PAD_FFT, STAGE_RADIAL,
                    STAGE_RADIAL_ADJ, STAGE_SPREAD, NufftError)
 
-__all__ = ["Plan", "Batch", "NufftProjector", "project", "NufftError", "version"]
+__all__ = ["Plan", "Batch", "NufftProjector", "project", "autotune", "NufftError", "version"]
 
 
 def _torch():
@@ -175,6 +175,23 @@ class Plan:
         cnt = (C.c_int64 * 8)()
         _lib.check(_lib.load().nufftct_get_stage_times(self._ptr, ms, cnt, 8))
         return {STAGE_NAMES[i]: (ms[i], cnt[i]) for i in range(len(STAGE_NAMES))}
+
+
+def autotune(N: int, K: int, J: int, dirs, n_r: int, *, kernel: str = "kb", beta=None,
+             dtype=None, deriv: bool = True) -> dict:
+    """Time candidate tilings for this radial geometry on the current GPU and
+    record the fastest; later Plans with the same shape use it."""
+    torch = _torch()
+    dtype = dtype or torch.complex64
+    prec = {torch.complex64: FP32, torch.complex128: FP64}[dtype]
+    d = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 3))
+    t, m, ms = C.c_int(), C.c_int(), C.c_double()
+    _lib.check(_lib.load().nufftct_autotune_radial(
+        int(N), int(K), int(J), {"kb": KERNEL_KB, "minmax": KERNEL_MINMAX_KB}[kernel],
+        -1.0 if beta is None else float(beta), prec, d.ctypes.data_as(C.POINTER(C.c_double)),
+        d.shape[0], int(n_r), RADIAL | (DERIV if deriv else 0), C.byref(t), C.byref(m), C.byref(ms),
+        C.c_void_p(_stream_handle())))
+    return {"tile": t.value, "max_pts": m.value, "ms": ms.value}
 
 
 class Batch:

@@ -25,6 +25,9 @@ SIGNATURES = {
                                       C.c_int, _dp, _i64, _i64, _p]),
     "nufftct_plan_create_radial": (C.c_int, [C.POINTER(_p), _i64, _i64, C.c_int, C.c_int,
                                              C.c_double, C.c_int, _dp, _i64, _i64, _p]),
+    "nufftct_autotune_radial": (C.c_int, [_i64, _i64, C.c_int, C.c_int, C.c_double, C.c_int, _dp,
+                                          _i64, _i64, C.c_int, C.POINTER(C.c_int),
+                                          C.POINTER(C.c_int), C.POINTER(C.c_double), _p]),
     "nufftct_forward": (C.c_int, [_p, _p, _p, C.c_int, _p]),
     "nufftct_adjoint": (C.c_int, [_p, _p, _p, C.c_int, _p]),
     "nufftct_stage": (C.c_int, [_p, C.c_int, _p, _p, C.c_int, _p]),

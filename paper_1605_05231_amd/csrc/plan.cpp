@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -237,9 +238,72 @@ static int validate(int64_t N, int64_t K, int J, int kernel, double beta, int pr
   return NUFFTCT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Autotuning of the tiling (tile edge, points per task).  Results live in a
+// process-wide table keyed by the plan's shape and are consulted by every plan
+// creation; NUFFTCT_TUNE_CACHE names an optional text file that persists them.
+struct TuneKey {
+  int64_t N, K;
+  int J, kernel, precision;
+  int64_t n_lines, n_r, M;
+  bool operator==(const TuneKey& o) const {
+    return N == o.N && K == o.K && J == o.J && kernel == o.kernel && precision == o.precision &&
+           n_lines == o.n_lines && n_r == o.n_r && M == o.M;
+  }
+};
+struct TuneVal {
+  int tile, max_pts;
+};
+static std::mutex g_tune_mu;
+static std::vector<std::pair<TuneKey, TuneVal>> g_tune;
+static bool g_tune_loaded = false;
+
+static void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = getenv("NUFFTCT_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = fopen(path, "r");
+  if (!f) return;
+  TuneKey k;
+  TuneVal v;
+  long long a[8];
+  while (fscanf(f, "%lld %lld %lld %lld %lld %lld %lld %lld %d %d", &a[0], &a[1], &a[2], &a[3],
+                &a[4], &a[5], &a[6], &a[7], &v.tile, &v.max_pts) == 10) {
+    k = TuneKey{a[0], a[1], (int)a[2], (int)a[3], (int)a[4], a[5], a[6], a[7]};
+    g_tune.push_back({k, v});
+  }
+  fclose(f);
+}
+
+static bool tune_lookup(const TuneKey& k, TuneVal* v) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  for (auto it = g_tune.rbegin(); it != g_tune.rend(); ++it)
+    if (it->first == k) {
+      *v = it->second;
+      return true;
+    }
+  return false;
+}
+
+static void tune_store(const TuneKey& k, const TuneVal& v) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  g_tune.push_back({k, v});
+  const char* path = getenv("NUFFTCT_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "%lld %lld %d %d %d %lld %lld %lld %d %d\n", (long long)k.N, (long long)k.K, k.J,
+          k.kernel, k.precision, (long long)k.n_lines, (long long)k.n_r, (long long)k.M, v.tile,
+          v.max_pts);
+  fclose(f);
+}
+
 static int create(nufftct_plan** out, int64_t N, int64_t K, int J, int kernel, double beta,
                   int precision, int64_t M, int64_t n_r, bool radial, const double* geom,
-                  int64_t n_geom, hipStream_t st) {
+                  int64_t n_geom, hipStream_t st, int tile_req, int maxpts_req) {
   if (!out) return fail(NUFFTCT_EINVAL, "out is NULL");
   *out = nullptr;
   if (!geom) return fail(NUFFTCT_EINVAL, "point/direction array is NULL");
@@ -265,9 +329,17 @@ static int create(nufftct_plan** out, int64_t N, int64_t K, int J, int kernel, d
   p->n_lines = radial ? n_geom : (n_r ? M / n_r : 0);
   // tile edge: divides K, J - 1 <= tile, and the spread's FP64 halo tile of
   // (tile + J - 1)^3 cells fits in LDS
+  // order of precedence: explicit request (autotuner) > environment > tuned
+  // table > default
+  TuneKey tkey{N, K, J, kernel, precision, p->n_lines, n_r, M};
+  TuneVal tuned{0, 0};
+  const bool have_tuned = tune_lookup(tkey, &tuned);
   {
     auto halo_bytes = [&](int t) { return (t + J - 1) * (t + J - 1) * (t + J - 1) * 16; };
-    int t = env_int("NUFFTCT_TILE", precision == NUFFTCT_FP32 ? 16 : 8);
+    int t = precision == NUFFTCT_FP32 ? 16 : 8;
+    if (have_tuned) t = tuned.tile;
+    t = env_int("NUFFTCT_TILE", t);
+    if (tile_req) t = tile_req;
     if (t != 8 && t != 16) t = 16;
     if (t == 16 && (K % 16 || halo_bytes(16) > 160 * 1024)) t = 8;
     if (K % t || J - 1 > t || halo_bytes(t) > 160 * 1024) {
@@ -277,7 +349,12 @@ static int create(nufftct_plan** out, int64_t N, int64_t K, int J, int kernel, d
     p->tile = t;
   }
   p->nb = (int)(K / p->tile);
-  p->max_pts = std::max(256, env_int("NUFFTCT_MAXPTS", 4096));
+  {
+    int mp = have_tuned ? tuned.max_pts : 4096;
+    mp = env_int("NUFFTCT_MAXPTS", mp);
+    if (maxpts_req) mp = maxpts_req;
+    p->max_pts = std::max(256, mp);
+  }
 
   auto bail = [&](int code) {
     free_plan(p);
@@ -525,7 +602,7 @@ int nufftct_plan_create(nufftct_plan** out, int64_t N, int64_t K, int J, int ker
                         int precision, const double* points, int64_t M, int64_t n_r,
                         void* stream) {
   return create(out, N, K, J, kernel, beta, precision, M, n_r, false, points, M,
-                (hipStream_t)stream);
+                (hipStream_t)stream, 0, 0);
 }
 
 int nufftct_plan_create_radial(nufftct_plan** out, int64_t N, int64_t K, int J, int kernel,
@@ -544,7 +621,70 @@ int nufftct_plan_create_radial(nufftct_plan** out, int64_t N, int64_t K, int J, 
     return fail(NUFFTCT_EINVAL, "n_lines * n_r must be < 2^31");
   }
   return create(out, N, K, J, kernel, beta, precision, n_lines * n_r, n_r, true, dirs, n_lines,
-                (hipStream_t)stream);
+                (hipStream_t)stream, 0, 0);
+}
+
+int nufftct_autotune_radial(int64_t N, int64_t K, int J, int kernel, double beta, int precision,
+                            const double* dirs, int64_t n_lines, int64_t n_r, int flags,
+                            int* best_tile, int* best_max_pts, double* best_ms, void* stream) {
+  if (n_lines < 1 || n_r < 4 || !dirs) return fail(NUFFTCT_EINVAL, "bad radial geometry");
+  if (flags & ~NUFFTCT_DERIV_RADIAL) return fail(NUFFTCT_EINVAL, "unknown flags %d", flags);
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t M = n_lines * n_r;
+  const size_t cxb = precision == NUFFTCT_FP64 ? 16 : 8;
+  void* vol = nullptr;
+  void* out = nullptr;
+  HIP_TRY(hipMalloc(&vol, (size_t)N * N * N * cxb));
+  if (hipMalloc(&out, (size_t)M * cxb) != hipSuccess) {
+    hipFree(vol);
+    return fail(NUFFTCT_ENOMEM, "autotune buffers");
+  }
+  // any non-zero pattern: the run time does not depend on the values
+  hipMemsetAsync(vol, 0x3c, (size_t)N * N * N * cxb, st);
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  const int tiles[2] = {16, 8};
+  const int mps[4] = {1024, 2048, 4096, 8192};
+  double best = 1e30;
+  TuneVal bv{0, 0};
+  for (int t : tiles)
+    for (int mp : mps) {
+      nufftct_plan* p = nullptr;
+      if (create(&p, N, K, J, kernel, beta, precision, M, n_r, true, dirs, n_lines, st, t, mp))
+        continue;  // e.g. the tile does not fit this (K, J) or memory ran out
+      if (p->tile != t) {  // the tile was adjusted: already covered by another candidate
+        free_plan(p);
+        continue;
+      }
+      int rc = nufftct_forward(p, vol, out, flags, stream);
+      if (!rc) rc = nufftct_adjoint(p, out, vol, flags, stream);
+      hipEventRecord(e0, st);
+      for (int r = 0; r < 2 && !rc; ++r) {
+        rc = nufftct_forward(p, vol, out, flags, stream);
+        if (!rc) rc = nufftct_adjoint(p, out, vol, flags, stream);
+      }
+      hipEventRecord(e1, st);
+      float ms = 0;
+      if (!rc && hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess &&
+          ms / 2 < best) {
+        best = ms / 2;
+        bv = TuneVal{t, mp};
+      }
+      hipStreamSynchronize(st);
+      free_plan(p);
+    }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipFree(vol);
+  hipFree(out);
+  if (bv.tile == 0) return fail(NUFFTCT_EHIP, "no autotune candidate ran");
+  tune_store(TuneKey{N, K, J, kernel, precision, n_lines, n_r, M}, bv);
+  if (best_tile) *best_tile = bv.tile;
+  if (best_max_pts) *best_max_pts = bv.max_pts;
+  if (best_ms) *best_ms = best;
+  g_err.clear();
+  return NUFFTCT_OK;
 }
 
 int nufftct_forward(nufftct_plan* p, const void* vol, void* out, int flags, void* stream) {

@@ -287,3 +287,19 @@ def test_tiling_and_split_tiles(monkeypatch, tile, maxpts):
     ea = rel_l2(a, projector.adjoint(y, dirs, n_r, prm))
     say(f"tile={tile} maxpts={maxpts} fwd={ef:.2e} adj={ea:.2e}")
     assert ef < 1e-5 and ea < 1e-5
+
+
+def test_autotune_records_and_is_used():
+    require_gpu()
+    import torch
+    import paper_1605_05231_amd as pkg
+    N, K, J, n_r = 32, 64, 6, 64
+    dirs = synthetic.line_directions(synthetic.azimuths(20), synthetic.polar_angles(10))
+    r = pkg.autotune(N, K, J, dirs, n_r)
+    say(f"autotune {r}")
+    assert r["tile"] in (8, 16) and r["max_pts"] in (1024, 2048, 4096, 8192) and r["ms"] > 0
+    plan = pkg.Plan(N, K, J, dirs=dirs, n_r=n_r)
+    prm = nufft.Params(N, K, J)
+    x = synthetic.ellipsoid_phantom(N, 6, 9).astype(np.complex64).astype(complex)
+    f = to_host(plan.forward(to_dev(x, torch.complex64)))
+    assert rel_l2(f, projector.forward(x, dirs, n_r, prm)) < 1e-5
