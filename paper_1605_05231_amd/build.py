@@ -12,6 +12,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libnufftct.so")
 BUILD = os.path.join(ROOT, "_build")
+# extra compile definitions for kernel-variant sweeps, e.g. "-DNUFFTCT_INTERP_NT=512"
+EXTRA = os.environ.get("NUFFTCT_EXTRA_FLAGS", "").split()
 
 SOURCES = ["plan.cpp", "tables.cpp", "batch.cpp", "k_fft_f32.hip", "k_fft_f64.hip",
            "k_grid_f32.hip", "k_grid_f64.hip"]
@@ -32,9 +34,9 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(BUILD, src + ".o")
-    cmd = [hipcc(), "-c", os.path.join(CSRC, src), "-o", obj] + COMMON + HOST_ONLY.get(src, [])
+def _compile(src: str, verbose: bool, build_dir: str) -> str:
+    obj = os.path.join(build_dir, src + ".o")
+    cmd = [hipcc(), "-c", os.path.join(CSRC, src), "-o", obj] + COMMON + EXTRA + HOST_ONLY.get(src, [])
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     if verbose:
@@ -45,21 +47,24 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False, jobs: int | None = None) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = False, jobs: int | None = None, out: str | None = None) -> str:
+    out = out or OUT
+    build_dir = BUILD if out == OUT else out + ".objs"
+    os.makedirs(build_dir, exist_ok=True)
     jobs = jobs or min(len(SOURCES), os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
-    tmp = OUT + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, verbose, build_dir), SOURCES))
+    tmp = out + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, OUT)
-    return OUT
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    args = [a for a in sys.argv[1:] if a != "-v"]
+    print(build(verbose="-v" in sys.argv, out=args[0] if args else None))

@@ -32,9 +32,12 @@ constexpr int nl_line() {  // lines per tile for line-major passes
   return target / L > 0 ? target / L : 1;
 }
 
+#ifndef NUFFTCT_FFT_COLS_F32
+#define NUFFTCT_FFT_COLS_F32 8
+#endif
 template <typename T, int L>
 constexpr int nl_col() {  // columns per tile for strided passes
-  if constexpr (sizeof(T) == 4) return L <= 512 ? 16 : 8;
+  if constexpr (sizeof(T) == 4) return L <= 512 ? NUFFTCT_FFT_COLS_F32 : 8;
   return L <= 512 ? 8 : 4;
 }
 

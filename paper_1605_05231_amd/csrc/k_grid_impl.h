@@ -27,7 +27,14 @@
 
 namespace kgrid {
 
+#ifndef NUFFTCT_INTERP_NT
+#define NUFFTCT_INTERP_NT 256
+#endif
+#ifndef NUFFTCT_INTERP_WAVES_PER_EU
+#define NUFFTCT_INTERP_WAVES_PER_EU 1
+#endif
 constexpr int NT = 256;
+constexpr int NT_INTERP = NUFFTCT_INTERP_NT;
 constexpr int NT_SPREAD = 1024;
 
 template <typename T>
@@ -37,23 +44,43 @@ __device__ __forceinline__ void lds_add(T* a, T v) {
   }
 }
 
-// First tap (centred, wrapped to [0, K)) and fractional offset per axis.
-__device__ __forceinline__ void point_taps(const PointGeom& g, int p, int J, int (&first)[3],
-                                           double (&frac)[3]) {
+// Raw geometry of one point as loaded from memory: the multiplier r and the
+// direction (radial plans: r = r_c, a = nhat_l) or r = 1 and a = omega (point
+// plans), so that omega = r * a in FP64 either way (exact for r = 1).  Loading
+// it is separated from using it so that the next point's loads can be issued
+// one iteration ahead.
+struct PtRaw {
+  int p;
+  double r, a0, a1, a2;
+};
+
+__device__ __forceinline__ PtRaw fetch_point(const PointGeom& g, const int32_t* __restrict__ perm,
+                                             int idx) {
 #pragma clang fp contract(off)
-  double om[3];
+  PtRaw q;
+  q.p = perm[idx];
   if (g.n_r) {
-    const int l = p / g.n_r;
-    const int c = p - l * g.n_r;
-    const double r = (double)(c - g.n_r / 2) * g.dr;
-    om[0] = r * g.dirs[3 * (int64_t)l + 0];
-    om[1] = r * g.dirs[3 * (int64_t)l + 1];
-    om[2] = r * g.dirs[3 * (int64_t)l + 2];
+    const int l = q.p / g.n_r;
+    const int c = q.p - l * g.n_r;
+    q.r = (double)(c - g.n_r / 2) * g.dr;
+    q.a0 = g.dirs[3 * (int64_t)l + 0];
+    q.a1 = g.dirs[3 * (int64_t)l + 1];
+    q.a2 = g.dirs[3 * (int64_t)l + 2];
   } else {
-    om[0] = g.pts[3 * (int64_t)p + 0];
-    om[1] = g.pts[3 * (int64_t)p + 1];
-    om[2] = g.pts[3 * (int64_t)p + 2];
+    q.r = 1.0;
+    q.a0 = g.pts[3 * (int64_t)q.p + 0];
+    q.a1 = g.pts[3 * (int64_t)q.p + 1];
+    q.a2 = g.pts[3 * (int64_t)q.p + 2];
   }
+  return q;
+}
+
+// First tap (centred, wrapped to [0, K)) and fractional offset per axis, with
+// the host binning's FP64 arithmetic (no contraction).
+__device__ __forceinline__ void point_taps(const PointGeom& g, const PtRaw& q, int J,
+                                           int (&first)[3], double (&frac)[3]) {
+#pragma clang fp contract(off)
+  const double om[3] = {q.r * q.a0, q.r * q.a1, q.r * q.a2};
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const double t = om[d] / g.gamma;
@@ -92,7 +119,8 @@ __device__ __forceinline__ int wrapK(int c, int K) { return c >= K ? c - K : c; 
 
 // ---------------------------------------------------------------------------
 template <typename T, int J, int TILE, bool CW, int DEG>
-__global__ __launch_bounds__(NT) void k_interp(const cx<T>* __restrict__ grid,
+__global__ __launch_bounds__(NT_INTERP)
+__attribute__((amdgpu_waves_per_eu(NUFFTCT_INTERP_WAVES_PER_EU))) void k_interp(const cx<T>* __restrict__ grid,
                                                cx<T>* __restrict__ out,
                                                const int32_t* __restrict__ perm,
                                                const TileTask* __restrict__ tasks,
@@ -106,17 +134,21 @@ __global__ __launch_bounds__(NT) void k_interp(const cx<T>* __restrict__ grid,
   const int K = g.K;
   const int b2 = tk.bin % nb, b1 = (tk.bin / nb) % nb, b0 = tk.bin / (nb * nb);
   const int o0 = b0 * TILE, o1 = b1 * TILE, o2 = b2 * TILE;
-  for (int idx = threadIdx.x; idx < S * S * S; idx += NT) {
+  for (int idx = threadIdx.x; idx < S * S * S; idx += NT_INTERP) {
     const int i2 = idx % S, i1 = (idx / S) % S, i0 = idx / (S * S);
     const int c0 = wrapK(o0 + i0, K), c1 = wrapK(o1 + i1, K), c2 = wrapK(o2 + i2, K);
     tile[idx] = grid[((int64_t)c0 * K + c1) * K + c2];
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < tk.count; i += NT) {
-    const int p = perm[tk.start + i];
+  PtRaw nxt;
+  if ((int)threadIdx.x < tk.count) nxt = fetch_point(g, perm, tk.start + threadIdx.x);
+  for (int i = threadIdx.x; i < tk.count; i += NT_INTERP) {
+    const PtRaw cur = nxt;
+    if (i + NT_INTERP < tk.count) nxt = fetch_point(g, perm, tk.start + i + NT_INTERP);
+    const int p = cur.p;
     int first[3];
     double frac[3];
-    point_taps(g, p, J, first, frac);
+    point_taps(g, cur, J, first, frac);
     T w0r[J], w0i[J], w1r[J], w1i[J], w2r[J], w2i[J];
     axis_weights<T, J, DEG, CW>(P, frac[0], w0r, w0i);
     axis_weights<T, J, DEG, CW>(P, frac[1], w1r, w1i);
@@ -228,13 +260,23 @@ __global__ __launch_bounds__(NT_SPREAD) void k_spread(const cx<T>* __restrict__ 
   } else {
     __syncthreads();
   }
+  PtRaw nxt;
+  cx<T> vnxt = {0, 0};
+  if ((int)threadIdx.x < tk.count) {
+    nxt = fetch_point(g, perm, tk.start + threadIdx.x);
+    vnxt = in[nxt.p];
+  }
   for (int i = threadIdx.x; i < tk.count; i += NT_SPREAD) {
-    const int p = perm[tk.start + i];
-    cx<T> v = in[p];
+    const PtRaw cur = nxt;
+    cx<T> v = vnxt;
+    if (i + NT_SPREAD < tk.count) {
+      nxt = fetch_point(g, perm, tk.start + i + NT_SPREAD);
+      vnxt = in[nxt.p];
+    }
     v = cx<T>{v.x * scale, v.y * scale};
     int first[3];
     double frac[3];
-    point_taps(g, p, J, first, frac);
+    point_taps(g, cur, J, first, frac);
     const int l0 = first[0] - o0, l1 = first[1] - o1, l2 = first[2] - o2;
     // the host bins with the same FP64 arithmetic, so every point of the task
     // lies in its tile; the check only keeps LDS accesses in bounds
@@ -283,33 +325,46 @@ __global__ __launch_bounds__(NT_SPREAD) void k_spread(const cx<T>* __restrict__ 
 // Spreading, phase 2 (owner computes): each grid cell is the fixed-order sum
 // of the halo partials that cover it -- those of every task of its own bin and
 // of the lower-neighbour bins whose halos reach it (J-1 cells into the tile).
-// One thread per cell, TILE^3 / NT blocks per tile: the cells' independent
-// loads give the memory system enough requests in flight.
+// One workgroup per tile and one thread per cell: the 8 source bins' task
+// ranges are read once per workgroup into LDS, then every cell issues its
+// (mostly single) partial loads independently.
 template <typename T, int TILE>
-__global__ __launch_bounds__(NT) void k_merge(const cx<T>* __restrict__ partials,
-                                              const int32_t* __restrict__ bin_tasks,
-                                              cx<T>* __restrict__ grid, int nb, int K, int S) {
+__global__ __launch_bounds__(TILE * TILE * TILE < 1024 ? TILE * TILE * TILE : 1024) void k_merge(
+    const cx<T>* __restrict__ partials, const int32_t* __restrict__ bin_tasks,
+    cx<T>* __restrict__ grid, int nb, int K, int S) {
   constexpr int TT = TILE * TILE * TILE;
-  constexpr int BPT = TT / NT;  // blocks per tile
-  static_assert(TT % NT == 0, "tile cells must be a multiple of the block size");
+  constexpr int NTM = TT < 1024 ? TT : 1024;
+  constexpr int PER = TT / NTM;
   const int64_t SS = (int64_t)S * S * S;
-  const int tile = (int)(blockIdx.x / BPT);
-  const int idx = (int)(blockIdx.x % BPT) * NT + (int)threadIdx.x;
+  const int tile = (int)blockIdx.x;
   const int t2 = tile % nb, t1 = (tile / nb) % nb, t0 = tile / (nb * nb);
-  const int i2 = idx % TILE, i1 = (idx / TILE) % TILE, i0 = idx / (TILE * TILE);
-  cx<T> acc = {0, 0};
-#pragma unroll
-  for (int delta = 0; delta < 8; ++delta) {
+  __shared__ int rng[16];
+  if (threadIdx.x < 8) {
+    const int delta = threadIdx.x;
     const int d0 = (delta >> 2) & 1, d1 = (delta >> 1) & 1, d2 = delta & 1;
-    // position of this cell inside the halo of bin (tile - delta)
-    const int q0 = i0 + d0 * TILE, q1 = i1 + d1 * TILE, q2 = i2 + d2 * TILE;
-    if (q0 < S && q1 < S && q2 < S) {
-      const int sb = (((t0 - d0 + nb) % nb) * nb + (t1 - d1 + nb) % nb) * nb + (t2 - d2 + nb) % nb;
-      const int64_t off = ((int64_t)q0 * S + q1) * S + q2;
-      for (int t = bin_tasks[sb]; t < bin_tasks[sb + 1]; ++t) acc = cadd(acc, partials[t * SS + off]);
-    }
+    const int sb = (((t0 - d0 + nb) % nb) * nb + (t1 - d1 + nb) % nb) * nb + (t2 - d2 + nb) % nb;
+    rng[2 * delta] = bin_tasks[sb];
+    rng[2 * delta + 1] = bin_tasks[sb + 1];
   }
-  grid[((int64_t)(t0 * TILE + i0) * K + (t1 * TILE + i1)) * K + (t2 * TILE + i2)] = acc;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int idx = (int)threadIdx.x + k * NTM;
+    const int i2 = idx % TILE, i1 = (idx / TILE) % TILE, i0 = idx / (TILE * TILE);
+    cx<T> acc = {0, 0};
+#pragma unroll
+    for (int delta = 0; delta < 8; ++delta) {
+      const int d0 = (delta >> 2) & 1, d1 = (delta >> 1) & 1, d2 = delta & 1;
+      // position of this cell inside the halo of bin (tile - delta)
+      const int q0 = i0 + d0 * TILE, q1 = i1 + d1 * TILE, q2 = i2 + d2 * TILE;
+      if (q0 < S && q1 < S && q2 < S) {
+        const int64_t off = ((int64_t)q0 * S + q1) * S + q2;
+        for (int t = rng[2 * delta]; t < rng[2 * delta + 1]; ++t)
+          acc = cadd(acc, partials[t * SS + off]);
+      }
+    }
+    grid[((int64_t)(t0 * TILE + i0) * K + (t1 * TILE + i1)) * K + (t2 * TILE + i2)] = acc;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -345,7 +400,7 @@ hipError_t launch_one(const nufftct_plan& p, const void* src, void* dst, hipStre
                          (const cx<T>*)src, (cx<T>*)p.d_partials, p.d_perm, p.d_tasks, p.xsplit,
                          g, p.nb, P);
     } else {
-      hipLaunchKernelGGL((k_interp<T, J, TILE, CW, DEG>), grd, dim3(NT), 0, st,
+      hipLaunchKernelGGL((k_interp<T, J, TILE, CW, DEG>), grd, dim3(NT_INTERP), 0, st,
                          (const cx<T>*)src, (cx<T>*)dst, p.d_perm, p.d_tasks, p.xsplit, g,
                          p.nb, P);
     }
@@ -386,12 +441,12 @@ hipError_t run(const nufftct_plan& p, const void* src, void* dst, hipStream_t st
 template <typename T>
 hipError_t merge(const nufftct_plan& p, void* grid, hipStream_t st) {
   const int S = p.tile + p.J - 1;
-  const dim3 grd((unsigned)((int64_t)p.nb * p.nb * p.nb * p.tile * p.tile * p.tile / NT));
+  const dim3 grd((unsigned)((int64_t)p.nb * p.nb * p.nb));
   if (p.tile == 16)
-    hipLaunchKernelGGL((k_merge<T, 16>), grd, dim3(NT), 0, st, (const cx<T>*)p.d_partials,
+    hipLaunchKernelGGL((k_merge<T, 16>), grd, dim3(1024), 0, st, (const cx<T>*)p.d_partials,
                        p.d_bin_tasks, (cx<T>*)grid, p.nb, (int)p.K, S);
   else if (p.tile == 8)
-    hipLaunchKernelGGL((k_merge<T, 8>), grd, dim3(NT), 0, st, (const cx<T>*)p.d_partials,
+    hipLaunchKernelGGL((k_merge<T, 8>), grd, dim3(512), 0, st, (const cx<T>*)p.d_partials,
                        p.d_bin_tasks, (cx<T>*)grid, p.nb, (int)p.K, S);
   else
     return hipErrorInvalidValue;
