@@ -16,6 +16,8 @@
 //            planes, storing all K.
 // Adjoint (A2+A1) mirrors it with inverse FFTs, storing only the N needed
 // outputs of each pass and fusing the crop and deapodization into pass x.
+// Both directions also skip the grid cells outside the ball that contains
+// every tap of every point (see k_fft_strided).
 #pragma once
 
 #include "cx.h"
@@ -91,12 +93,20 @@ __global__ __launch_bounds__(NT) void k_pad_fft_x(const cx<T>* __restrict__ vol,
 //   outer index o: pruned -> plane (o - N/2) mod K for o < N; else o < K
 //   load_pruned : only rows whose centred index lies in [-N/2, N/2) are read
 //   store_pruned: only those rows are written
+// Ball pruning (r2 = R^2, +inf disables it): only cells whose centred
+// frequency (kappa = j - K/2 on each transformed axis) satisfies
+// kappa_row^2 + [kappa_outer^2] + kappa_col^2 <= R^2 are ever read by the
+// interpolation or non-zero after the spread (every tap lies within J sqrt(3)/2
+// of a point with |t| <= R0).  ball = 1: store only such rows (forward);
+// ball = 2: load only such rows, the rest being zero (adjoint).  outer_in_ball
+// says whether the outer index is a transformed (centred) axis.
 template <typename T, int L, int S>
 __global__ __launch_bounds__(NT) void k_fft_strided(cx<T>* __restrict__ grid,
                                                     const cx<T>* __restrict__ tw, int N,
                                                     int64_t row_stride, int64_t outer_stride,
                                                     int outer_pruned, int load_pruned,
-                                                    int store_pruned) {
+                                                    int store_pruned, double r2, int ball,
+                                                    int outer_in_ball) {
   constexpr int NL = nl_col<T, L>();
   constexpr int K = L;
   __shared__ cx<T> buf[fft::tile_elems<false, L, NL>()];
@@ -104,12 +114,36 @@ __global__ __launch_bounds__(NT) void k_fft_strided(cx<T>* __restrict__ grid,
   const int h = N / 2;
   const int o = blockIdx.y;
   const int qo = outer_pruned ? wrap_of(o - h, K) : o;
-  cx<T>* base = grid + (int64_t)qo * outer_stride + (int64_t)blockIdx.x * NL;
+  const int col0 = blockIdx.x * NL;
+  cx<T>* base = grid + (int64_t)qo * outer_stride + col0;
+  // squared distance of this block's nearest column from the ball's axis
+  const double ko = outer_in_ball ? (double)(qo - K / 2) : 0.0;
+  double kc_min = 0.0;
+  if (col0 > K / 2) kc_min = (double)(col0 - K / 2);
+  else if (col0 + NL - 1 < K / 2) kc_min = (double)(K / 2 - (col0 + NL - 1));
+  const bool block_out = ball && ko * ko + kc_min * kc_min > r2;
+  if (block_out) {
+    // nothing of this block is ever needed; the adjoint still owes zeros to
+    // the rows the next pass reads
+    if (ball == 2) {
+      for (int idx = tid; idx < NL * L; idx += NT) {
+        const int line = idx % NL, e = idx / NL;
+        const int m = centred_of(e, K);
+        if (!store_pruned || (m >= -h && m < h)) base[e * row_stride + line] = cx<T>{0, 0};
+      }
+    }
+    return;
+  }
   for (int idx = tid; idx < NL * L; idx += NT) {
     const int line = idx % NL, e = idx / NL;
     cx<T> v = {0, 0};
     const int m = centred_of(e, K);
-    if (!load_pruned || (m >= -h && m < h)) v = base[e * row_stride + line];
+    bool ld = !load_pruned || (m >= -h && m < h);
+    if (ball == 2) {
+      const double kr = (double)(e - K / 2), kc = (double)(col0 + line - K / 2);
+      ld = ld && kr * kr + ko * ko + kc * kc <= r2;
+    }
+    if (ld) v = base[e * row_stride + line];
     buf[idx] = v;  // column-major address e*NL + line
   }
   __syncthreads();
@@ -117,7 +151,12 @@ __global__ __launch_bounds__(NT) void k_fft_strided(cx<T>* __restrict__ grid,
   for (int idx = tid; idx < NL * L; idx += NT) {
     const int line = idx % NL, e = idx / NL;
     const int m = centred_of(e, K);
-    if (!store_pruned || (m >= -h && m < h)) base[e * row_stride + line] = buf[idx];
+    bool stv = !store_pruned || (m >= -h && m < h);
+    if (ball == 1) {
+      const double kr = (double)(e - K / 2), kc = (double)(col0 + line - K / 2);
+      stv = stv && kr * kr + ko * ko + kc * kc <= r2;
+    }
+    if (stv) base[e * row_stride + line] = buf[idx];
   }
 }
 
@@ -216,8 +255,11 @@ __global__ __launch_bounds__(NT) void k_radial(const cx<T>* __restrict__ in,
   X(16) X(32) X(48) X(64) X(80) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(512) X(640) X(768) X(1024)
 
 template <typename T>
-hipError_t pad_fft(const nufftct_plan& p, const void* vol, void* grid, hipStream_t st) {
+hipError_t pad_fft(const nufftct_plan& p, const void* vol, void* grid, hipStream_t st,
+                   bool prune) {
   const int N = (int)p.N, K = (int)p.K;
+  const double r2 = prune ? p.ball_r2 : 1e300;
+  const int ball = prune && r2 < 1e299 ? 1 : 0;
   const cx<T>* tw = (const cx<T>*)p.d_tw_K;
   cx<T>* g = (cx<T>*)grid;
   switch (K) {
@@ -229,9 +271,9 @@ hipError_t pad_fft(const nufftct_plan& p, const void* vol, void* grid, hipStream
     hipLaunchKernelGGL((k_pad_fft_x<T, LL>), dim3((unsigned)((nlines + NLx - 1) / NLx)),      \
                        dim3(NT), 0, st, (const cx<T>*)vol, g, p.d_s, tw, N);                  \
     hipLaunchKernelGGL((k_fft_strided<T, LL, -1>), dim3(LL / NLc, N), dim3(NT), 0, st, g, tw, \
-                       N, (int64_t)LL, (int64_t)LL * LL, 1, 1, 0);                            \
+                       N, (int64_t)LL, (int64_t)LL * LL, 1, 1, 0, r2, ball, 0);              \
     hipLaunchKernelGGL((k_fft_strided<T, LL, -1>), dim3(LL / NLc, LL), dim3(NT), 0, st, g,    \
-                       tw, N, (int64_t)LL * LL, (int64_t)LL, 0, 1, 0);                        \
+                       tw, N, (int64_t)LL * LL, (int64_t)LL, 0, 1, 0, r2, ball, 1);          \
     return hipGetLastError();                                                                 \
   }
     KFFT_SIZES(CASE)
@@ -242,8 +284,10 @@ hipError_t pad_fft(const nufftct_plan& p, const void* vol, void* grid, hipStream
 }
 
 template <typename T>
-hipError_t ifft_crop(const nufftct_plan& p, void* grid, void* vol, hipStream_t st) {
+hipError_t ifft_crop(const nufftct_plan& p, void* grid, void* vol, hipStream_t st, bool prune) {
   const int N = (int)p.N, K = (int)p.K;
+  const double r2 = prune ? p.ball_r2 : 1e300;
+  const int ball = prune && r2 < 1e299 ? 2 : 0;
   const cx<T>* tw = (const cx<T>*)p.d_tw_K;
   cx<T>* g = (cx<T>*)grid;
   switch (K) {
@@ -253,9 +297,9 @@ hipError_t ifft_crop(const nufftct_plan& p, void* grid, void* vol, hipStream_t s
     constexpr int NLc = nl_col<T, LL>();                                                      \
     const int64_t nlines = (int64_t)N * N;                                                    \
     hipLaunchKernelGGL((k_fft_strided<T, LL, +1>), dim3(LL / NLc, LL), dim3(NT), 0, st, g,    \
-                       tw, N, (int64_t)LL * LL, (int64_t)LL, 0, 0, 1);                        \
+                       tw, N, (int64_t)LL * LL, (int64_t)LL, 0, 0, 1, r2, ball, 1);          \
     hipLaunchKernelGGL((k_fft_strided<T, LL, +1>), dim3(LL / NLc, N), dim3(NT), 0, st, g, tw, \
-                       N, (int64_t)LL, (int64_t)LL * LL, 1, 0, 1);                            \
+                       N, (int64_t)LL, (int64_t)LL * LL, 1, 0, 1, r2, ball, 0);              \
     hipLaunchKernelGGL((k_ifft_crop_x<T, LL>), dim3((unsigned)((nlines + NLx - 1) / NLx)),    \
                        dim3(NT), 0, st, (const cx<T>*)g, (cx<T>*)vol, p.d_s, tw, N);          \
     return hipGetLastError();                                                                 \
@@ -298,13 +342,13 @@ hipError_t radial(const nufftct_plan& p, const void* in, void* out, bool adj, bo
 #define KFFT_INSTANTIATE(T)                                                                \
   template <>                                                                              \
   hipError_t launch_pad_fft<T>(const nufftct_plan& p, const void* vol, void* grid,         \
-                               hipStream_t s) {                                            \
-    return kfft::pad_fft<T>(p, vol, grid, s);                                              \
+                               hipStream_t s, bool prune) {                                \
+    return kfft::pad_fft<T>(p, vol, grid, s, prune);                                       \
   }                                                                                        \
   template <>                                                                              \
   hipError_t launch_ifft_crop<T>(const nufftct_plan& p, void* grid, void* vol,             \
-                                 hipStream_t s) {                                          \
-    return kfft::ifft_crop<T>(p, grid, vol, s);                                            \
+                                 hipStream_t s, bool prune) {                              \
+    return kfft::ifft_crop<T>(p, grid, vol, s, prune);                                     \
   }                                                                                        \
   template <>                                                                              \
   hipError_t launch_radial<T>(const nufftct_plan& p, const void* in, void* out, bool adj,  \

@@ -331,13 +331,25 @@ __global__ __launch_bounds__(NT_SPREAD) void k_spread(const cx<T>* __restrict__ 
 template <typename T, int TILE>
 __global__ __launch_bounds__(TILE * TILE * TILE < 1024 ? TILE * TILE * TILE : 1024) void k_merge(
     const cx<T>* __restrict__ partials, const int32_t* __restrict__ bin_tasks,
-    cx<T>* __restrict__ grid, int nb, int K, int S) {
+    cx<T>* __restrict__ grid, int nb, int K, int S, double r2) {
   constexpr int TT = TILE * TILE * TILE;
   constexpr int NTM = TT < 1024 ? TT : 1024;
   constexpr int PER = TT / NTM;
   const int64_t SS = (int64_t)S * S * S;
   const int tile = (int)blockIdx.x;
   const int t2 = tile % nb, t1 = (tile / nb) % nb, t0 = tile / (nb * nb);
+  {
+    // tiles wholly outside the ball holding every tap are never read
+    double d2 = 0.0;
+    const int ts[3] = {t0, t1, t2};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int lo = ts[d] * TILE - K / 2, hi = lo + TILE - 1;
+      const double c = lo > 0 ? (double)lo : (hi < 0 ? (double)(-hi) : 0.0);
+      d2 += c * c;
+    }
+    if (d2 > r2) return;
+  }
   __shared__ int rng[16];
   if (threadIdx.x < 8) {
     const int delta = threadIdx.x;
@@ -439,15 +451,16 @@ hipError_t run(const nufftct_plan& p, const void* src, void* dst, hipStream_t st
 }
 
 template <typename T>
-hipError_t merge(const nufftct_plan& p, void* grid, hipStream_t st) {
+hipError_t merge(const nufftct_plan& p, void* grid, hipStream_t st, bool prune) {
   const int S = p.tile + p.J - 1;
+  const double r2 = prune ? p.ball_r2 : 1e300;
   const dim3 grd((unsigned)((int64_t)p.nb * p.nb * p.nb));
   if (p.tile == 16)
     hipLaunchKernelGGL((k_merge<T, 16>), grd, dim3(1024), 0, st, (const cx<T>*)p.d_partials,
-                       p.d_bin_tasks, (cx<T>*)grid, p.nb, (int)p.K, S);
+                       p.d_bin_tasks, (cx<T>*)grid, p.nb, (int)p.K, S, r2);
   else if (p.tile == 8)
     hipLaunchKernelGGL((k_merge<T, 8>), grd, dim3(512), 0, st, (const cx<T>*)p.d_partials,
-                       p.d_bin_tasks, (cx<T>*)grid, p.nb, (int)p.K, S);
+                       p.d_bin_tasks, (cx<T>*)grid, p.nb, (int)p.K, S, r2);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -467,6 +480,6 @@ hipError_t merge(const nufftct_plan& p, void* grid, hipStream_t st) {
     return kgrid::run<T, true>(p, in, grid, s);                                             \
   }                                                                                         \
   template <>                                                                               \
-  hipError_t launch_merge<T>(const nufftct_plan& p, void* grid, hipStream_t s) {            \
-    return kgrid::merge<T>(p, grid, s);                                                     \
+  hipError_t launch_merge<T>(const nufftct_plan& p, void* grid, hipStream_t s, bool prune) { \
+    return kgrid::merge<T>(p, grid, s, prune);                                              \
   }

@@ -419,6 +419,27 @@ static int create(nufftct_plan** out, int64_t N, int64_t K, int J, int kernel, d
     if ((rc = upload((void**)&p->d_pts, g.data(), g.size(), st))) return bail(rc);
   }
 
+  // ball holding every tap: |t| <= t_max for every point, taps within
+  // J sqrt(3)/2 of t; one extra cell of margin
+  {
+    double tmax = 0.0;
+    if (radial) {
+      for (int64_t l = 0; l < n_geom; ++l) {
+        const double nn = std::sqrt(g[3 * l] * g[3 * l] + g[3 * l + 1] * g[3 * l + 1] +
+                                    g[3 * l + 2] * g[3 * l + 2]);
+        tmax = std::max(tmax, nn * M_PI * (double)K / (2.0 * M_PI));
+      }
+    } else {
+      for (int64_t i = 0; i < M; ++i) {
+        const double nn = std::sqrt(g[3 * i] * g[3 * i] + g[3 * i + 1] * g[3 * i + 1] +
+                                    g[3 * i + 2] * g[3 * i + 2]);
+        tmax = std::max(tmax, nn * (double)K / (2.0 * M_PI));
+      }
+    }
+    const double R = tmax * (1.0 + 1e-12) + 0.5 * std::sqrt(3.0) * J + 1.0;
+    p->ball_r2 = R < 0.5 * std::sqrt(3.0) * (double)K ? R * R : 1e300;
+  }
+
   // binning
   {
     Binning B;
@@ -514,14 +535,16 @@ struct StageTimer {
   }
 };
 
+// prune: grid cells outside the taps' ball are neither produced nor read
+// (the operator paths); the single-stage entry point works on full grids
 template <typename T>
 static hipError_t run_stage(nufftct_plan* p, int stage, const void* in, void* out, int flags,
-                            hipStream_t st) {
+                            hipStream_t st, bool prune) {
   StageTimer tm(p, st, stage);
   hipError_t e = hipSuccess;
   switch (stage) {
     case NUFFTCT_STAGE_PAD_FFT:
-      e = launch_pad_fft<T>(*p, in, out, st);
+      e = launch_pad_fft<T>(*p, in, out, st, prune);
       break;
     case NUFFTCT_STAGE_INTERP:
       e = launch_interp<T>(*p, in, out, st);
@@ -538,13 +561,13 @@ static hipError_t run_stage(nufftct_plan* p, int stage, const void* in, void* ou
       e = launch_spread<T>(*p, in, out, st);
       tm.done();
       StageTimer tr(p, st, NUFFTCT_TIMING_MERGE);
-      if (e == hipSuccess) e = launch_merge<T>(*p, out, st);
+      if (e == hipSuccess) e = launch_merge<T>(*p, out, st, prune);
       tr.done();
       break;
     }
     case NUFFTCT_STAGE_IFFT_CROP:
       // in-place on `in` (a K^3 grid the caller or the plan owns)
-      e = launch_ifft_crop<T>(*p, const_cast<void*>(in), out, st);
+      e = launch_ifft_crop<T>(*p, const_cast<void*>(in), out, st, prune);
       break;
     default:
       e = hipErrorInvalidValue;
@@ -573,12 +596,12 @@ static int check_call(nufftct_plan* p, const void* a, void* b, int flags) {
 
 template <typename T>
 static int forward_impl(nufftct_plan* p, const void* vol, void* out, int flags, hipStream_t st) {
-  STAGE_TRY(run_stage<T>(p, NUFFTCT_STAGE_PAD_FFT, vol, p->d_grid, flags, st));
+  STAGE_TRY(run_stage<T>(p, NUFFTCT_STAGE_PAD_FFT, vol, p->d_grid, flags, st, true));
   if (flags & NUFFTCT_RADIAL) {
-    STAGE_TRY(run_stage<T>(p, NUFFTCT_STAGE_INTERP, p->d_grid, p->d_tmp, flags, st));
-    STAGE_TRY(run_stage<T>(p, NUFFTCT_STAGE_RADIAL, p->d_tmp, out, flags, st));
+    STAGE_TRY(run_stage<T>(p, NUFFTCT_STAGE_INTERP, p->d_grid, p->d_tmp, flags, st, true));
+    STAGE_TRY(run_stage<T>(p, NUFFTCT_STAGE_RADIAL, p->d_tmp, out, flags, st, true));
   } else {
-    STAGE_TRY(run_stage<T>(p, NUFFTCT_STAGE_INTERP, p->d_grid, out, flags, st));
+    STAGE_TRY(run_stage<T>(p, NUFFTCT_STAGE_INTERP, p->d_grid, out, flags, st, true));
   }
   return NUFFTCT_OK;
 }
@@ -587,11 +610,11 @@ template <typename T>
 static int adjoint_impl(nufftct_plan* p, const void* in, void* vol, int flags, hipStream_t st) {
   const void* src = in;
   if (flags & NUFFTCT_RADIAL) {
-    STAGE_TRY(run_stage<T>(p, NUFFTCT_STAGE_RADIAL_ADJ, in, p->d_tmp, flags, st));
+    STAGE_TRY(run_stage<T>(p, NUFFTCT_STAGE_RADIAL_ADJ, in, p->d_tmp, flags, st, true));
     src = p->d_tmp;
   }
-  STAGE_TRY(run_stage<T>(p, NUFFTCT_STAGE_SPREAD, src, p->d_grid, flags, st));
-  STAGE_TRY(run_stage<T>(p, NUFFTCT_STAGE_IFFT_CROP, p->d_grid, vol, flags, st));
+  STAGE_TRY(run_stage<T>(p, NUFFTCT_STAGE_SPREAD, src, p->d_grid, flags, st, true));
+  STAGE_TRY(run_stage<T>(p, NUFFTCT_STAGE_IFFT_CROP, p->d_grid, vol, flags, st, true));
   return NUFFTCT_OK;
 }
 
@@ -716,8 +739,8 @@ int nufftct_stage(nufftct_plan* p, int stage, const void* in, void* out, int fla
     HIP_TRY(hipMemcpyAsync(p->d_grid, in, p->grid_bytes, hipMemcpyDeviceToDevice, st));
     src = p->d_grid;
   }
-  hipError_t e = p->precision == NUFFTCT_FP32 ? run_stage<float>(p, stage, src, out, flags, st)
-                                              : run_stage<double>(p, stage, src, out, flags, st);
+  hipError_t e = p->precision == NUFFTCT_FP32 ? run_stage<float>(p, stage, src, out, flags, st, false)
+                                              : run_stage<double>(p, stage, src, out, flags, st, false);
   if (e != hipSuccess) return fail(NUFFTCT_EHIP, "launch failed: %s", hipGetErrorString(e));
   return NUFFTCT_OK;
 }

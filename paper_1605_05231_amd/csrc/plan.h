@@ -51,6 +51,9 @@ struct nufftct_plan {
   int tile = 16;      // tile edge in grid cells
   int nb = 0;         // tiles per axis
   int max_pts = 4096; // points per task
+  // squared radius (in grid cells, centred) of the ball holding every tap of
+  // every point; +inf when it would not prune anything
+  double ball_r2 = 1e300;
 
   // device memory owned by the plan
   double* d_dirs = nullptr;
@@ -93,10 +96,14 @@ struct nufftct_plan {
 
 // ---- launchers (return hipSuccess or the launch error) ----
 // FFT stages (k_fft_*.hip), templated on the real type
+// prune: skip grid cells outside the ball that holds every tap (forward and
+// adjoint paths); the single-stage entry point produces and reads full grids
 template <typename T>
-hipError_t launch_pad_fft(const nufftct_plan& p, const void* vol, void* grid, hipStream_t s);
+hipError_t launch_pad_fft(const nufftct_plan& p, const void* vol, void* grid, hipStream_t s,
+                          bool prune);
 template <typename T>
-hipError_t launch_ifft_crop(const nufftct_plan& p, void* grid, void* vol, hipStream_t s);
+hipError_t launch_ifft_crop(const nufftct_plan& p, void* grid, void* vol, hipStream_t s,
+                            bool prune);
 template <typename T>
 hipError_t launch_radial(const nufftct_plan& p, const void* in, void* out, bool adjoint,
                          bool deriv, hipStream_t s);
@@ -107,7 +114,7 @@ template <typename T>
 hipError_t launch_spread(const nufftct_plan& p, const void* in, void* grid, hipStream_t s);
 hipError_t launch_zero(void* ptr, size_t bytes, hipStream_t s);
 template <typename T>
-hipError_t launch_merge(const nufftct_plan& p, void* grid, hipStream_t s);
+hipError_t launch_merge(const nufftct_plan& p, void* grid, hipStream_t s, bool prune);
 
 bool fft_length_supported(int64_t L);
 // record this thread's error message (read back by nufftct_last_error); returns code
