@@ -117,6 +117,84 @@ __device__ __forceinline__ void axis_weights(const WeightPoly<T, DEG>& P, double
 
 __device__ __forceinline__ int wrapK(int c, int K) { return c >= K ? c - K : c; }
 
+// Innermost pitch of the interpolation's staged halo tile: for FP32, S rounded
+// up to even, so that a row's start parity equals its first tap's parity and
+// pairs of complex values can be read as aligned 16-byte words.
+template <typename T>
+constexpr int interp_pitch(int S) { return sizeof(T) == 4 ? S + (S & 1) : S; }
+
+// Read J consecutive complex values of a staged row starting at element rs.
+// PAIRS (FP32 only): aligned 16-byte reads of value pairs, EVEN tells the
+// parity of rs (even: J/2 pair reads; odd: one 8-byte read, then pairs),
+// halving the LDS instructions of the gather.
+template <typename T, int J, bool PAIRS, bool EVEN>
+__device__ __forceinline__ void read_row(const cx<T>* tile, int rs, cx<T> (&v)[J]) {
+  if constexpr (PAIRS) {
+    static_assert(sizeof(T) == 4, "pair reads are for FP32 complex values");
+    const float4* q = reinterpret_cast<const float4*>(tile);
+    constexpr int k0 = EVEN ? 0 : 1;
+    if constexpr (!EVEN) v[0] = tile[rs];
+#pragma unroll
+    for (int k = k0; k + 1 < J; k += 2) {
+      const float4 w = q[(rs + k) >> 1];
+      v[k] = cx<T>{w.x, w.y};
+      v[k + 1] = cx<T>{w.z, w.w};
+    }
+    if constexpr (((J - k0) & 1) != 0) v[J - 1] = tile[rs + J - 1];
+  } else {
+#pragma unroll
+    for (int k = 0; k < J; ++k) v[k] = tile[rs + k];
+  }
+}
+
+// Unroll factor of the gather's outermost tap loop: full unrolling lets the
+// compiler hoist every row read of a point and spill.
+#ifndef NUFFTCT_GATHER_UNROLL
+#define NUFFTCT_GATHER_UNROLL 1
+#endif
+#define NUFFTCT_PRAGMA_(x) _Pragma(#x)
+#define NUFFTCT_UNROLL_(n) NUFFTCT_PRAGMA_(unroll n)
+
+template <typename T, int J, bool CW>
+__device__ __forceinline__ cx<T> wmac(cx<T> acc, cx<T> v, T wr, T wi) {
+  if constexpr (CW) return cadd(acc, cmul(v, cx<T>{wr, wi}));
+  return cx<T>{acc.x + wr * v.x, acc.y + wr * v.y};
+}
+
+// Separable J^3 gather of one point.  MODE 0: taps inside the staged tile
+// are read from LDS one value at a time, others from the global grid;
+// MODE 1 / 2: every tap is inside and the first tap's cell is even / odd,
+// rows are read with pair reads.
+template <typename T, int J, int S, int S2, bool CW, int MODE>
+__device__ __forceinline__ cx<T> gather(const cx<T>* tile, const cx<T>* __restrict__ grid, int K,
+                                        const int (&first)[3], int l0, int l1, int l2, bool inside,
+                                        const T (&w0r)[J], const T (&w0i)[J], const T (&w1r)[J],
+                                        const T (&w1i)[J], const T (&w2r)[J], const T (&w2i)[J]) {
+  cx<T> acc = {0, 0};
+  NUFFTCT_UNROLL_(NUFFTCT_GATHER_UNROLL)
+  for (int a = 0; a < J; ++a) {
+    cx<T> acc_a = {0, 0};
+#pragma unroll
+    for (int b = 0; b < J; ++b) {
+      cx<T> acc_b = {0, 0};
+      cx<T> rv[J];
+      if (MODE != 0 || inside) {
+        read_row<T, J, MODE != 0, MODE == 1>(tile, ((l0 + a) * S + (l1 + b)) * S2 + l2, rv);
+      } else {
+        const int c0 = wrapK(first[0] + a, K), c1 = wrapK(first[1] + b, K);
+        const cx<T>* row = grid + ((int64_t)c0 * K + c1) * K;
+#pragma unroll
+        for (int c = 0; c < J; ++c) rv[c] = row[wrapK(first[2] + c, K)];
+      }
+#pragma unroll
+      for (int c = 0; c < J; ++c) acc_b = wmac<T, J, CW>(acc_b, rv[c], w2r[c], w2i[c]);
+      acc_a = wmac<T, J, CW>(acc_a, acc_b, w1r[b], w1i[b]);
+    }
+    acc = wmac<T, J, CW>(acc, acc_a, w0r[a], w0i[a]);
+  }
+  return acc;
+}
+
 // ---------------------------------------------------------------------------
 template <typename T, int J, int TILE, bool CW, int DEG>
 __global__ __launch_bounds__(NT_INTERP)
@@ -127,7 +205,9 @@ __attribute__((amdgpu_waves_per_eu(NUFFTCT_INTERP_WAVES_PER_EU))) void k_interp(
                                                XcdSplit xs, PointGeom g,
                                                int nb, WeightPoly<T, DEG> P) {
   constexpr int S = TILE + J - 1;
-  __shared__ cx<T> tile[S * S * S];
+  constexpr int S2 = interp_pitch<T>(S);
+  __shared__ float4 tile_mem[(S * S * S2 * (int)sizeof(cx<T>) + 15) / 16];
+  cx<T>* tile = reinterpret_cast<cx<T>*>(tile_mem);
   const int64_t task_id = xcd_task(blockIdx.x, xs);
   if (task_id < 0) return;
   const TileTask tk = tasks[task_id];
@@ -137,7 +217,7 @@ __attribute__((amdgpu_waves_per_eu(NUFFTCT_INTERP_WAVES_PER_EU))) void k_interp(
   for (int idx = threadIdx.x; idx < S * S * S; idx += NT_INTERP) {
     const int i2 = idx % S, i1 = (idx / S) % S, i0 = idx / (S * S);
     const int c0 = wrapK(o0 + i0, K), c1 = wrapK(o1 + i1, K), c2 = wrapK(o2 + i2, K);
-    tile[idx] = grid[((int64_t)c0 * K + c1) * K + c2];
+    tile[(i0 * S + i1) * S2 + i2] = grid[((int64_t)c0 * K + c1) * K + c2];
   }
   __syncthreads();
   PtRaw nxt;
@@ -156,53 +236,25 @@ __attribute__((amdgpu_waves_per_eu(NUFFTCT_INTERP_WAVES_PER_EU))) void k_interp(
     const int l0 = first[0] - o0, l1 = first[1] - o1, l2 = first[2] - o2;
     const bool inside = (unsigned)l0 < (unsigned)TILE && (unsigned)l1 < (unsigned)TILE &&
                         (unsigned)l2 < (unsigned)TILE;
-    cx<T> acc = {0, 0};
-#pragma unroll
-    for (int a = 0; a < J; ++a) {
-      cx<T> acc_a = {0, 0};
-#pragma unroll
-      for (int b = 0; b < J; ++b) {
-        cx<T> acc_b = {0, 0};
-        if (inside) {
-          const cx<T>* row = &tile[((l0 + a) * S + (l1 + b)) * S + l2];
-#pragma unroll
-          for (int c = 0; c < J; ++c) {
-            const cx<T> v = row[c];
-            if constexpr (CW) {
-              acc_b = cadd(acc_b, cmul(v, cx<T>{w2r[c], w2i[c]}));
-            } else {
-              acc_b.x += w2r[c] * v.x;
-              acc_b.y += w2r[c] * v.y;
-            }
-          }
-        } else {
-          const int c0 = wrapK(first[0] + a, K), c1 = wrapK(first[1] + b, K);
-          const cx<T>* row = grid + ((int64_t)c0 * K + c1) * K;
-#pragma unroll
-          for (int c = 0; c < J; ++c) {
-            const cx<T> v = row[wrapK(first[2] + c, K)];
-            if constexpr (CW) {
-              acc_b = cadd(acc_b, cmul(v, cx<T>{w2r[c], w2i[c]}));
-            } else {
-              acc_b.x += w2r[c] * v.x;
-              acc_b.y += w2r[c] * v.y;
-            }
-          }
-        }
-        if constexpr (CW) {
-          acc_a = cadd(acc_a, cmul(acc_b, cx<T>{w1r[b], w1i[b]}));
-        } else {
-          acc_a.x += w1r[b] * acc_b.x;
-          acc_a.y += w1r[b] * acc_b.y;
-        }
-      }
-      if constexpr (CW) {
-        acc = cadd(acc, cmul(acc_a, cx<T>{w0r[a], w0i[a]}));
-      } else {
-        acc.x += w0r[a] * acc_a.x;
-        acc.y += w0r[a] * acc_a.y;
+    // The host orders each task's points even cells first, so whole waves
+    // usually agree on the parity and take a pair-read path.
+    cx<T> acc;
+    bool done = false;
+    if constexpr (sizeof(T) == 4) {
+      const bool even = (l2 & 1) == 0;
+      if (__all(inside && even)) {
+        acc = gather<T, J, S, S2, CW, 1>(tile, grid, K, first, l0, l1, l2, inside, w0r, w0i, w1r,
+                                         w1i, w2r, w2i);
+        done = true;
+      } else if (__all(inside && !even)) {
+        acc = gather<T, J, S, S2, CW, 2>(tile, grid, K, first, l0, l1, l2, inside, w0r, w0i, w1r,
+                                         w1i, w2r, w2i);
+        done = true;
       }
     }
+    if (!done)
+      acc = gather<T, J, S, S2, CW, 0>(tile, grid, K, first, l0, l1, l2, inside, w0r, w0i, w1r,
+                                       w1i, w2r, w2i);
     out[p] = acc;
   }
 }
@@ -409,7 +461,7 @@ hipError_t launch_one(const nufftct_plan& p, const void* src, void* dst, hipStre
     const PointGeom g = p.geom();
     if (SPREAD) {
       hipLaunchKernelGGL((k_spread<T, J, TILE, CW, DEG>), grd, dim3(NT_SPREAD), 0, st,
-                         (const cx<T>*)src, (cx<T>*)p.d_partials, p.d_perm, p.d_tasks, p.xsplit,
+                         (const cx<T>*)src, (cx<T>*)p.d_partials, p.d_perm_s, p.d_tasks, p.xsplit,
                          g, p.nb, P);
     } else {
       hipLaunchKernelGGL((k_interp<T, J, TILE, CW, DEG>), grd, dim3(NT_INTERP), 0, st,

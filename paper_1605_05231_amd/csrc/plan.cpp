@@ -101,24 +101,32 @@ static void point_omega(const nufftct_plan& p, const std::vector<double>& geom, 
 #pragma clang fp contract(on)
 
 struct Binning {
-  std::vector<int32_t> perm;
+  std::vector<int32_t> perm;    // interpolation order
+  std::vector<int32_t> perm_s;  // spreading order (same tasks)
   std::vector<TileTask> tasks;
   std::vector<int32_t> bin_tasks;  // nbins + 1 offsets into tasks
 };
 
 // Sort points by the tile of their first tap and cut every bin into tasks of
-// at most max_pts points.  Within a task the points are then interleaved by
-// the LDS bank of their first tap's cell in the staged halo tile: with cell
-// c = (l0 S + l1) S + l2 (S = tile + J - 1), points are dealt round-robin over
-// the residues c mod 32, so the 32 lanes of a half-wave start on distinct
-// 8-byte bank pairs and a tap offset shared by all lanes keeps them distinct.
+// at most max_pts points.  Within a task the points are then ordered by the
+// LDS bank of their first tap's cell in the staged halo tile, once for each
+// of the two kernels that read the order:
+//   spreading: cell c = (l0 S + l1) S + l2 (S = tile + J - 1); points dealt
+//     round-robin over the residues c mod 32, so the lanes of a wave start
+//     on distinct banks and a tap offset shared by all lanes keeps them so;
+//   interpolation (FP32): rows padded to even pitch S2, cell
+//     c = (l0 S + l1) S2 + l2; even cells first, then odd ones (a wave's
+//     row reads then share one alignment), each class dealt round-robin over
+//     its 16 residues mod 32.  FP64 interpolation uses the spreading order.
 static void build_bins(const nufftct_plan& p, const std::vector<double>& geom, Binning& B) {
   const int64_t M = p.M;
   const int nb = p.nb, T = p.tile, J = p.J;
   const int S = T + J - 1;
+  const bool pairs = p.precision == NUFFTCT_FP32;
+  const int S2 = pairs ? S + (S & 1) : S;
   const int64_t nbins = (int64_t)nb * nb * nb;
   std::vector<int32_t> key(M);
-  std::vector<uint8_t> res(M);
+  std::vector<uint8_t> res_s(M), res_i(M);
   const double gamma = (2.0 * M_PI) / (double)p.K;
   unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   if (M < 200000) nth = 1;
@@ -135,17 +143,18 @@ static void build_bins(const nufftct_plan& p, const std::vector<double>& geom, B
       point_omega(p, geom, i, om);
       host_first_taps(om, J, p.K, gamma, first);
       key[i] = (int32_t)(((int64_t)(first[0] / T) * nb + first[1] / T) * nb + first[2] / T);
-      const int c = ((first[0] % T) * S + first[1] % T) * S + first[2] % T;
-      res[i] = (uint8_t)(c & 31);
+      const int r01 = (first[0] % T) * S + first[1] % T;
+      res_s[i] = (uint8_t)((r01 * S + first[2] % T) & 31);
+      res_i[i] = (uint8_t)((r01 * S2 + first[2] % T) & 31);
     }
   });
   std::vector<int64_t> off(nbins + 1, 0);
   for (int64_t i = 0; i < M; ++i) off[key[i] + 1]++;
   for (int64_t k = 0; k < nbins; ++k) off[k + 1] += off[k];
-  B.perm.resize(M);
+  B.perm_s.resize(M);
   {
     std::vector<int64_t> pos(off.begin(), off.end() - 1);
-    for (int64_t i = 0; i < M; ++i) B.perm[pos[key[i]]++] = (int32_t)i;
+    for (int64_t i = 0; i < M; ++i) B.perm_s[pos[key[i]]++] = (int32_t)i;
   }
   B.tasks.clear();
   B.bin_tasks.assign(nbins + 1, 0);
@@ -162,24 +171,38 @@ static void build_bins(const nufftct_plan& p, const std::vector<double>& geom, B
     }
   }
   B.bin_tasks[nbins] = (int32_t)B.tasks.size();
-  // deal each task's points round-robin over the 32 bank residues
+  B.perm = B.perm_s;
+  // Reorder pts[0..n) by residue: classes of residues r = cls, cls + step, ...
+  // in turn, each dealt round-robin over its residues.
+  struct Deal {
+    std::vector<int32_t> tmp, bucket, cnt = std::vector<int32_t>(33), fill;
+    void run(int32_t* pts, int n, const uint8_t* res, int step) {
+      std::fill(cnt.begin(), cnt.end(), 0);
+      for (int i = 0; i < n; ++i) cnt[res[pts[i]] + 1]++;
+      for (int r = 0; r < 32; ++r) cnt[r + 1] += cnt[r];
+      tmp.assign(pts, pts + n);
+      bucket.resize(n);
+      fill.assign(cnt.begin(), cnt.end() - 1);
+      for (int i = 0; i < n; ++i) bucket[fill[res[tmp[i]]]++] = tmp[i];
+      int o = 0;
+      for (int cls = 0; cls < step; ++cls) {
+        int left = 0;
+        for (int r = cls; r < 32; r += step) left += cnt[r + 1] - cnt[r];
+        for (int round = 0; left > 0; ++round)
+          for (int r = cls; r < 32; r += step)
+            if (cnt[r] + round < cnt[r + 1]) {
+              pts[o++] = bucket[cnt[r] + round];
+              --left;
+            }
+      }
+    }
+  };
   parallel((int64_t)B.tasks.size(), [&](int64_t a, int64_t b) {
-    std::vector<int32_t> tmp;
-    std::vector<int32_t> cnt(33);
+    Deal d;
     for (int64_t k = a; k < b; ++k) {
       const TileTask& t = B.tasks[k];
-      int32_t* pts = B.perm.data() + t.start;
-      std::fill(cnt.begin(), cnt.end(), 0);
-      for (int i = 0; i < t.count; ++i) cnt[res[pts[i]] + 1]++;
-      for (int r = 0; r < 32; ++r) cnt[r + 1] += cnt[r];
-      tmp.assign(pts, pts + t.count);
-      std::vector<int32_t> bucket(t.count);
-      std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
-      for (int i = 0; i < t.count; ++i) bucket[fill[res[tmp[i]]]++] = tmp[i];
-      int o = 0;
-      for (int round = 0; o < t.count; ++round)
-        for (int r = 0; r < 32; ++r)
-          if (cnt[r] + round < cnt[r + 1]) pts[o++] = bucket[cnt[r] + round];
+      d.run(B.perm_s.data() + t.start, t.count, res_s.data(), 1);
+      d.run(B.perm.data() + t.start, t.count, pairs ? res_i.data() : res_s.data(), pairs ? 2 : 1);
     }
   });
 }
@@ -193,6 +216,7 @@ static void free_plan(nufftct_plan* p) {
   hipFree(p->d_tw_K);
   hipFree(p->d_tw_r);
   hipFree(p->d_perm);
+  hipFree(p->d_perm_s);
   hipFree(p->d_tasks);
   hipFree(p->d_bin_tasks);
   hipFree(p->d_partials);
@@ -464,6 +488,7 @@ static int create(nufftct_plan** out, int64_t N, int64_t K, int J, int kernel, d
       p->xsplit.max_len = std::max(p->xsplit.max_len, 1);
     }
     if ((rc = upload((void**)&p->d_perm, B.perm.data(), B.perm.size(), st))) return bail(rc);
+    if ((rc = upload((void**)&p->d_perm_s, B.perm_s.data(), B.perm_s.size(), st))) return bail(rc);
     if ((rc = upload((void**)&p->d_tasks, B.tasks.data(), B.tasks.size(), st))) return bail(rc);
     if ((rc = upload((void**)&p->d_bin_tasks, B.bin_tasks.data(), B.bin_tasks.size(), st)))
       return bail(rc);

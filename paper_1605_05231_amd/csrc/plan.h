@@ -61,7 +61,8 @@ struct nufftct_plan {
   double* d_s = nullptr;        // deapodization s(m), N doubles
   void* d_tw_K = nullptr;       // twiddles for length K (plan precision)
   void* d_tw_r = nullptr;       // twiddles for length n_r
-  int32_t* d_perm = nullptr;       // M point ids sorted by tile
+  int32_t* d_perm = nullptr;       // M point ids sorted by tile (interpolation order)
+  int32_t* d_perm_s = nullptr;     // the same, spreading order within each task
   TileTask* d_tasks = nullptr;     // tasks: a bin and <= max_pts of its points
   int64_t ntasks = 0;
   XcdSplit xsplit{};               // per-XCD task ranges of equal point count
