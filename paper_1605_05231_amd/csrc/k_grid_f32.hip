@@ -1,6 +1,17 @@
 // Interpolation / spreading kernels instantiated for FP32 (complex64), and
 // the fill kernel used to clear workspaces (kept as a kernel so that it can
 // be captured in HIP graphs).
+// FP32 spreading keeps one 8-byte accumulator per halo cell (74 KB for
+// tile 16, J = 6), so two workgroups share a CU; 512 threads each within
+// 128 VGPRs (measured faster than 1024 threads within 64).
+#ifndef NUFFTCT_SPREAD32_NT
+#define NUFFTCT_SPREAD32_NT 512
+#endif
+#ifndef NUFFTCT_SPREAD32_WAVES
+#define NUFFTCT_SPREAD32_WAVES 4
+#endif
+#define NUFFTCT_SPREAD_NT NUFFTCT_SPREAD32_NT
+#define NUFFTCT_SPREAD_WAVES_PER_EU NUFFTCT_SPREAD32_WAVES
 #include "k_grid_impl.h"
 KGRID_INSTANTIATE(float)
 

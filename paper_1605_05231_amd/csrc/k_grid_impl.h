@@ -35,7 +35,13 @@ namespace kgrid {
 #endif
 constexpr int NT = 256;
 constexpr int NT_INTERP = NUFFTCT_INTERP_NT;
-constexpr int NT_SPREAD = 1024;
+#ifndef NUFFTCT_SPREAD_NT
+#define NUFFTCT_SPREAD_NT 1024
+#endif
+#ifndef NUFFTCT_SPREAD_WAVES_PER_EU
+#define NUFFTCT_SPREAD_WAVES_PER_EU 1
+#endif
+constexpr int NT_SPREAD = NUFFTCT_SPREAD_NT;
 
 template <typename T>
 __device__ __forceinline__ void lds_add(T* a, T v) {
@@ -267,34 +273,42 @@ __attribute__((amdgpu_waves_per_eu(NUFFTCT_INTERP_WAVES_PER_EU))) void k_interp(
 //
 // LDS accumulation (f32 LDS atomic adds run ~8x slower than 64-bit ones on
 // gfx950):
-//   FP32 path: each contribution is quantised to an integer of magnitude
-//     < 2^31 with the task's scale 2^28 / max|component of its inputs| and
-//     summed exactly in 64-bit integers (ds_add_u64), so the per-contribution
-//     error is <= 2^-29 of the task's largest input and the sum is
-//     independent of the order of the atomics (bitwise reproducible).
-//   FP64 form: FP64 atomic adds (ds_add_f64).
+//   FP32 path: exact integer sums, both components in one 64-bit word.  With
+//     the task's scale s = 2^30 / (vmax B) (2^29 for complex weights), vmax
+//     the largest component of the task's inputs and B the plan-time bound on
+//     sum_points prod_axes |w| at any cell of the halo (k_spread_bound), every
+//     cell's sums of rounded contributions q = rn(s u) stay inside
+//     [-2^31, 2^31).  Each tap adds the word q_re 2^32 + q_im (two's
+//     complement) with one ds_add_u64; the low half of a sum is then the sum
+//     of q_im and the rest the sum of q_re, the carries between them being
+//     exact.  The per-contribution error is <= 0.5 / s, and the sum does not
+//     depend on the order of the atomics (bitwise reproducible).
+//   FP64 form: FP64 atomic adds (ds_add_f64) on planar real / imaginary
+//     accumulators.
 template <typename T, int J, int TILE, bool CW, int DEG>
-__global__ __launch_bounds__(NT_SPREAD) void k_spread(const cx<T>* __restrict__ in,
+__global__ __launch_bounds__(NT_SPREAD)
+__attribute__((amdgpu_waves_per_eu(NUFFTCT_SPREAD_WAVES_PER_EU))) void k_spread(const cx<T>* __restrict__ in,
                                                       cx<T>* __restrict__ partials,
                                                       const int32_t* __restrict__ perm,
                                                       const TileTask* __restrict__ tasks,
+                                                      const float* __restrict__ bound,
                                                       XcdSplit xs, PointGeom g, int nb,
                                                       WeightPoly<T, DEG> P) {
   constexpr bool FIXED = sizeof(T) == 4;
   constexpr int S = TILE + J - 1;
   constexpr int SS = S * S * S;
-  // planar accumulators (all real parts, then all imaginary parts): a wave's
-  // 64-bit atomics then spread over every LDS bank instead of half of them.
-  // FP64 sums, or int64 sums on the FP32 path.
-  __shared__ double acc[2 * SS];
+  // FP32: one packed 64-bit word per cell.  FP64: planar accumulators (all
+  // real parts, then all imaginary parts), so that a wave's 64-bit atomics
+  // spread over every LDS bank instead of half of them.
+  __shared__ double acc[FIXED ? SS : 2 * SS];
   __shared__ unsigned int s_maxbits;
-  long long* acci = reinterpret_cast<long long*>(acc);
+  unsigned long long* accp = reinterpret_cast<unsigned long long*>(acc);
   const int64_t task_id = xcd_task(blockIdx.x, xs);
   if (task_id < 0) return;
   const TileTask tk = tasks[task_id];
   const int b2 = tk.bin % nb, b1 = (tk.bin / nb) % nb, b0 = tk.bin / (nb * nb);
   const int o0 = b0 * TILE, o1 = b1 * TILE, o2 = b2 * TILE;
-  for (int idx = threadIdx.x; idx < 2 * SS; idx += NT_SPREAD) acc[idx] = 0.0;
+  for (int idx = threadIdx.x; idx < (FIXED ? SS : 2 * SS); idx += NT_SPREAD) acc[idx] = 0.0;
   T scale = (T)1;
   if constexpr (FIXED) {
     if (threadIdx.x == 0) s_maxbits = 0u;
@@ -308,7 +322,8 @@ __global__ __launch_bounds__(NT_SPREAD) void k_spread(const cx<T>* __restrict__ 
     atomicMax(&s_maxbits, __float_as_uint(m));
     __syncthreads();
     const float vmax = __uint_as_float(s_maxbits);
-    scale = vmax > 0.f ? 268435456.0f / vmax : 1.0f;  // 2^28 / max
+    const float vb = vmax * bound[task_id];
+    scale = vb > 0.f ? (CW ? 536870912.0f : 1073741824.0f) / vb : 1.0f;  // 2^29 or 2^30
   } else {
     __syncthreads();
   }
@@ -353,8 +368,9 @@ __global__ __launch_bounds__(NT_SPREAD) void k_spread(const cx<T>* __restrict__ 
           const cx<T> u =
               CW ? cmulc(vb, cx<T>{w2r[c], w2i[c]}) : cx<T>{w2r[c] * vb.x, w2r[c] * vb.y};
           if constexpr (FIXED) {
-            lds_add(&acci[row + c], (long long)__float2int_rn(u.x));
-            lds_add(&acci[SS + row + c], (long long)__float2int_rn(u.y));
+            const long long qr = __float2int_rn(u.x), qi = __float2int_rn(u.y);
+            lds_add(&accp[row + c],
+                    ((unsigned long long)qr << 32) + (unsigned long long)qi);
           } else {
             lds_add(&acc[row + c], (double)u.x);
             lds_add(&acc[SS + row + c], (double)u.y);
@@ -367,10 +383,76 @@ __global__ __launch_bounds__(NT_SPREAD) void k_spread(const cx<T>* __restrict__ 
   cx<T>* dst = partials + task_id * (int64_t)SS;
   if constexpr (FIXED) {
     const double inv = 1.0 / (double)scale;
-    for (int idx = threadIdx.x; idx < SS; idx += NT_SPREAD)
-      dst[idx] = cx<T>{(T)((double)acci[idx] * inv), (T)((double)acci[SS + idx] * inv)};
+    for (int idx = threadIdx.x; idx < SS; idx += NT_SPREAD) {
+      const unsigned long long w = accp[idx];
+      const long long lo = (long long)(int)(unsigned int)(w & 0xffffffffull);
+      const long long hi = (long long)(w - (unsigned long long)lo) >> 32;
+      dst[idx] = cx<T>{(T)((double)hi * inv), (T)((double)lo * inv)};
+    }
   } else {
     for (int idx = threadIdx.x; idx < SS; idx += NT_SPREAD) dst[idx] = cx<T>{(T)acc[idx], (T)acc[SS + idx]};
+  }
+}
+
+// Plan-time bound for the FP32 spreading scale: per task, the largest over
+// its halo cells of sum_points prod_axes |w_axis| (the weights the spreading
+// evaluates), accumulated exactly in 2^-32 units with every term rounded up,
+// then rounded up to float.
+template <typename T, int J, int TILE, bool CW, int DEG>
+__global__ __launch_bounds__(NT_SPREAD) void k_spread_bound(float* __restrict__ bound,
+                                                            const int32_t* __restrict__ perm,
+                                                            const TileTask* __restrict__ tasks,
+                                                            XcdSplit xs, PointGeom g, int nb,
+                                                            WeightPoly<T, DEG> P) {
+  constexpr int S = TILE + J - 1;
+  constexpr int SS = S * S * S;
+  __shared__ unsigned long long acc[SS];
+  __shared__ unsigned long long s_max;
+  const int64_t task_id = xcd_task(blockIdx.x, xs);
+  if (task_id < 0) return;
+  const TileTask tk = tasks[task_id];
+  const int b2 = tk.bin % nb, b1 = (tk.bin / nb) % nb, b0 = tk.bin / (nb * nb);
+  const int o0 = b0 * TILE, o1 = b1 * TILE, o2 = b2 * TILE;
+  for (int idx = threadIdx.x; idx < SS; idx += NT_SPREAD) acc[idx] = 0ull;
+  if (threadIdx.x == 0) s_max = 0ull;
+  __syncthreads();
+  for (int i = threadIdx.x; i < tk.count; i += NT_SPREAD) {
+    const PtRaw cur = fetch_point(g, perm, tk.start + i);
+    int first[3];
+    double frac[3];
+    point_taps(g, cur, J, first, frac);
+    const int l0 = first[0] - o0, l1 = first[1] - o1, l2 = first[2] - o2;
+    if ((unsigned)l0 >= (unsigned)TILE || (unsigned)l1 >= (unsigned)TILE ||
+        (unsigned)l2 >= (unsigned)TILE)
+      continue;
+    T w0r[J], w0i[J], w1r[J], w1i[J], w2r[J], w2i[J];
+    axis_weights<T, J, DEG, CW>(P, frac[0], w0r, w0i);
+    axis_weights<T, J, DEG, CW>(P, frac[1], w1r, w1i);
+    axis_weights<T, J, DEG, CW>(P, frac[2], w2r, w2i);
+    double m0[J], m1[J], m2[J];
+#pragma unroll
+    for (int a = 0; a < J; ++a) {
+      m0[a] = sqrt((double)w0r[a] * w0r[a] + (double)w0i[a] * w0i[a]);
+      m1[a] = sqrt((double)w1r[a] * w1r[a] + (double)w1i[a] * w1i[a]);
+      m2[a] = sqrt((double)w2r[a] * w2r[a] + (double)w2i[a] * w2i[a]);
+    }
+    for (int a = 0; a < J; ++a)
+      for (int b = 0; b < J; ++b) {
+        const int row = ((l0 + a) * S + (l1 + b)) * S + l2;
+        const double mab = m0[a] * m1[b] * 4294967296.0;  // 2^32
+#pragma unroll
+        for (int c = 0; c < J; ++c)
+          lds_add(&acc[row + c], (unsigned long long)ceil(mab * m2[c] * (1.0 + 1e-12)));
+      }
+  }
+  __syncthreads();
+  unsigned long long m = 0ull;
+  for (int idx = threadIdx.x; idx < SS; idx += NT_SPREAD) m = acc[idx] > m ? acc[idx] : m;
+  __hip_atomic_fetch_max(&s_max, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double b = (double)s_max * (1.0 / 4294967296.0) * (1.0 + 1e-6);
+    bound[task_id] = __double2float_ru(b);
   }
 }
 
@@ -450,19 +532,24 @@ constexpr bool tile_fits() {  // the spread's FP64 halo tile must fit in LDS
   return (TILE + J - 1) * (TILE + J - 1) * (TILE + J - 1) * 16 <= 160 * 1024 && J - 1 <= TILE;
 }
 
-template <typename T, int J, int TILE, bool CW, bool SPREAD>
+enum Op { OP_INTERP = 0, OP_SPREAD = 1, OP_BOUND = 2 };
+
+template <typename T, int J, int TILE, bool CW, int OP>
 hipError_t launch_one(const nufftct_plan& p, const void* src, void* dst, hipStream_t st) {
-  if constexpr (!tile_fits<T, J, TILE>()) {
+  if constexpr (!tile_fits<T, J, TILE>() || (OP == OP_BOUND && sizeof(T) != 4)) {
     return hipErrorInvalidValue;
   } else {
     constexpr int DEG = PolyOf<T>::DEG;
     const auto& P = PolyOf<T>::get(p);
     const dim3 grd((unsigned)((int64_t)p.xsplit.max_len * NUFFTCT_NUM_XCD));
     const PointGeom g = p.geom();
-    if (SPREAD) {
+    if constexpr (OP == OP_SPREAD) {
       hipLaunchKernelGGL((k_spread<T, J, TILE, CW, DEG>), grd, dim3(NT_SPREAD), 0, st,
-                         (const cx<T>*)src, (cx<T>*)p.d_partials, p.d_perm_s, p.d_tasks, p.xsplit,
-                         g, p.nb, P);
+                         (const cx<T>*)src, (cx<T>*)p.d_partials, p.d_perm_s, p.d_tasks,
+                         p.d_bound, p.xsplit, g, p.nb, P);
+    } else if constexpr (OP == OP_BOUND) {
+      hipLaunchKernelGGL((k_spread_bound<T, J, TILE, CW, DEG>), grd, dim3(NT_SPREAD), 0, st,
+                         p.d_bound, p.d_perm_s, p.d_tasks, p.xsplit, g, p.nb, P);
     } else {
       hipLaunchKernelGGL((k_interp<T, J, TILE, CW, DEG>), grd, dim3(NT_INTERP), 0, st,
                          (const cx<T>*)src, (cx<T>*)dst, p.d_perm, p.d_tasks, p.xsplit, g,
@@ -472,34 +559,34 @@ hipError_t launch_one(const nufftct_plan& p, const void* src, void* dst, hipStre
   }
 }
 
-template <typename T, int J, bool CW, bool SPREAD>
+template <typename T, int J, bool CW, int OP>
 hipError_t by_tile(const nufftct_plan& p, const void* src, void* dst, hipStream_t st) {
   switch (p.tile) {
-    case 8: return launch_one<T, J, 8, CW, SPREAD>(p, src, dst, st);
-    case 16: return launch_one<T, J, 16, CW, SPREAD>(p, src, dst, st);
+    case 8: return launch_one<T, J, 8, CW, OP>(p, src, dst, st);
+    case 16: return launch_one<T, J, 16, CW, OP>(p, src, dst, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <typename T, bool CW, bool SPREAD>
+template <typename T, bool CW, int OP>
 hipError_t by_j(const nufftct_plan& p, const void* src, void* dst, hipStream_t st) {
   switch (p.J) {
-    case 2: return by_tile<T, 2, CW, SPREAD>(p, src, dst, st);
-    case 3: return by_tile<T, 3, CW, SPREAD>(p, src, dst, st);
-    case 4: return by_tile<T, 4, CW, SPREAD>(p, src, dst, st);
-    case 5: return by_tile<T, 5, CW, SPREAD>(p, src, dst, st);
-    case 6: return by_tile<T, 6, CW, SPREAD>(p, src, dst, st);
-    case 7: return by_tile<T, 7, CW, SPREAD>(p, src, dst, st);
-    case 8: return by_tile<T, 8, CW, SPREAD>(p, src, dst, st);
+    case 2: return by_tile<T, 2, CW, OP>(p, src, dst, st);
+    case 3: return by_tile<T, 3, CW, OP>(p, src, dst, st);
+    case 4: return by_tile<T, 4, CW, OP>(p, src, dst, st);
+    case 5: return by_tile<T, 5, CW, OP>(p, src, dst, st);
+    case 6: return by_tile<T, 6, CW, OP>(p, src, dst, st);
+    case 7: return by_tile<T, 7, CW, OP>(p, src, dst, st);
+    case 8: return by_tile<T, 8, CW, OP>(p, src, dst, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <typename T, bool SPREAD>
+template <typename T, int OP>
 hipError_t run(const nufftct_plan& p, const void* src, void* dst, hipStream_t st) {
   if (p.ntasks == 0) return hipSuccess;
-  if (p.kernel == NUFFTCT_KERNEL_MINMAX_KB) return by_j<T, true, SPREAD>(p, src, dst, st);
-  return by_j<T, false, SPREAD>(p, src, dst, st);
+  if (p.kernel == NUFFTCT_KERNEL_MINMAX_KB) return by_j<T, true, OP>(p, src, dst, st);
+  return by_j<T, false, OP>(p, src, dst, st);
 }
 
 template <typename T>
@@ -524,12 +611,16 @@ hipError_t merge(const nufftct_plan& p, void* grid, hipStream_t st, bool prune) 
   template <>                                                                               \
   hipError_t launch_interp<T>(const nufftct_plan& p, const void* grid, void* out,           \
                               hipStream_t s) {                                              \
-    return kgrid::run<T, false>(p, grid, out, s);                                           \
+    return kgrid::run<T, kgrid::OP_INTERP>(p, grid, out, s);                                           \
   }                                                                                         \
   template <>                                                                               \
   hipError_t launch_spread<T>(const nufftct_plan& p, const void* in, void* grid,            \
                               hipStream_t s) {                                              \
-    return kgrid::run<T, true>(p, in, grid, s);                                             \
+    return kgrid::run<T, kgrid::OP_SPREAD>(p, in, grid, s);                                 \
+  }                                                                                         \
+  template <>                                                                               \
+  hipError_t launch_spread_bound<T>(const nufftct_plan& p, hipStream_t s) {                 \
+    return kgrid::run<T, kgrid::OP_BOUND>(p, nullptr, nullptr, s);                          \
   }                                                                                         \
   template <>                                                                               \
   hipError_t launch_merge<T>(const nufftct_plan& p, void* grid, hipStream_t s, bool prune) { \

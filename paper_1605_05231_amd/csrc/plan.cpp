@@ -220,6 +220,7 @@ static void free_plan(nufftct_plan* p) {
   hipFree(p->d_tasks);
   hipFree(p->d_bin_tasks);
   hipFree(p->d_partials);
+  hipFree(p->d_bound);
   hipFree(p->d_grid);
   hipFree(p->d_tmp);
   for (auto& e : p->events) {
@@ -523,6 +524,21 @@ static int create(nufftct_plan** out, int64_t N, int64_t K, int J, int kernel, d
     if (e != hipSuccess) {
       free_plan(p);
       return fail(NUFFTCT_ENOMEM, "workspace of %zu bytes: %s", p->tmp_bytes, hipGetErrorString(e));
+    }
+  }
+  // FP32 spreading: per-task bounds that set its fixed-point scale
+  if (precision == NUFFTCT_FP32) {
+    const size_t bbytes = (size_t)std::max<int64_t>(p->ntasks, 1) * sizeof(float);
+    hipError_t e = hipMalloc(&p->d_bound, bbytes);
+    if (e != hipSuccess) {
+      free_plan(p);
+      return fail(NUFFTCT_ENOMEM, "spread bounds of %zu bytes: %s", bbytes, hipGetErrorString(e));
+    }
+    e = launch_spread_bound<float>(*p, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      free_plan(p);
+      return fail(NUFFTCT_EHIP, "spread bound kernel failed: %s", hipGetErrorString(e));
     }
   }
   *out = p;

@@ -68,6 +68,7 @@ struct nufftct_plan {
   XcdSplit xsplit{};               // per-XCD task ranges of equal point count
   int32_t* d_bin_tasks = nullptr;  // nb^3 + 1 offsets: tasks of bin b are [o[b], o[b+1])
   void* d_partials = nullptr;      // per task, its spread halo tile (S^3 complex)
+  float* d_bound = nullptr;        // FP32: per task, max over halo cells of sum |w|
   void* d_grid = nullptr;       // K^3 complex workspace
   void* d_tmp = nullptr;        // M complex workspace
   size_t grid_bytes = 0, tmp_bytes = 0, partial_bytes = 0;
@@ -113,6 +114,10 @@ template <typename T>
 hipError_t launch_interp(const nufftct_plan& p, const void* grid, void* out, hipStream_t s);
 template <typename T>
 hipError_t launch_spread(const nufftct_plan& p, const void* in, void* grid, hipStream_t s);
+// FP32 plans, at creation: per task, the bound on the summed weight
+// magnitudes at any halo cell that sets the spreading's fixed-point scale
+template <typename T>
+hipError_t launch_spread_bound(const nufftct_plan& p, hipStream_t s);
 hipError_t launch_zero(void* ptr, size_t bytes, hipStream_t s);
 template <typename T>
 hipError_t launch_merge(const nufftct_plan& p, void* grid, hipStream_t s, bool prune);
