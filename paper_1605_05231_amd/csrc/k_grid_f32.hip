@@ -12,6 +12,20 @@
 #endif
 #define NUFFTCT_SPREAD_NT NUFFTCT_SPREAD32_NT
 #define NUFFTCT_SPREAD_WAVES_PER_EU NUFFTCT_SPREAD32_WAVES
+// FP32 interpolation: two 512-thread workgroups per CU (LDS-bound) within
+// 128 VGPRs, which leaves no room for a one-ahead prefetch of the point data.
+#ifndef NUFFTCT_INTERP32_NT
+#define NUFFTCT_INTERP32_NT 512
+#endif
+#ifndef NUFFTCT_INTERP32_WAVES
+#define NUFFTCT_INTERP32_WAVES 4
+#endif
+#ifndef NUFFTCT_INTERP32_PREFETCH
+#define NUFFTCT_INTERP32_PREFETCH 0
+#endif
+#define NUFFTCT_INTERP_NT NUFFTCT_INTERP32_NT
+#define NUFFTCT_INTERP_WAVES_PER_EU NUFFTCT_INTERP32_WAVES
+#define NUFFTCT_INTERP_PREFETCH NUFFTCT_INTERP32_PREFETCH
 #include "k_grid_impl.h"
 KGRID_INSTANTIATE(float)
 

@@ -30,8 +30,14 @@ namespace kgrid {
 #ifndef NUFFTCT_INTERP_NT
 #define NUFFTCT_INTERP_NT 256
 #endif
+#ifndef NUFFTCT_INTERP_PREFETCH
+#define NUFFTCT_INTERP_PREFETCH 1
+#endif
 #ifndef NUFFTCT_INTERP_WAVES_PER_EU
 #define NUFFTCT_INTERP_WAVES_PER_EU 1
+#endif
+#ifndef NUFFTCT_MERGE_V2
+#define NUFFTCT_MERGE_V2 1
 #endif
 constexpr int NT = 256;
 constexpr int NT_INTERP = NUFFTCT_INTERP_NT;
@@ -226,11 +232,17 @@ __attribute__((amdgpu_waves_per_eu(NUFFTCT_INTERP_WAVES_PER_EU))) void k_interp(
     tile[(i0 * S + i1) * S2 + i2] = grid[((int64_t)c0 * K + c1) * K + c2];
   }
   __syncthreads();
+#if NUFFTCT_INTERP_PREFETCH
   PtRaw nxt;
   if ((int)threadIdx.x < tk.count) nxt = fetch_point(g, perm, tk.start + threadIdx.x);
+#endif
   for (int i = threadIdx.x; i < tk.count; i += NT_INTERP) {
+#if NUFFTCT_INTERP_PREFETCH
     const PtRaw cur = nxt;
     if (i + NT_INTERP < tk.count) nxt = fetch_point(g, perm, tk.start + i + NT_INTERP);
+#else
+    const PtRaw cur = fetch_point(g, perm, tk.start + i);
+#endif
     const int p = cur.p;
     int first[3];
     double frac[3];
@@ -498,6 +510,33 @@ __global__ __launch_bounds__(TILE * TILE * TILE < 1024 ? TILE * TILE * TILE : 10
     const int idx = (int)threadIdx.x + k * NTM;
     const int i2 = idx % TILE, i1 = (idx / TILE) % TILE, i0 = idx / (TILE * TILE);
     cx<T> acc = {0, 0};
+#if NUFFTCT_MERGE_V2
+    // the first task of every source bin: eight independent loads (a source
+    // that does not reach this cell reads a dummy word and adds zero), then
+    // the further tasks of the bins that have several; a fixed order
+    int64_t off[8];
+    bool hit[8];
+#pragma unroll
+    for (int delta = 0; delta < 8; ++delta) {
+      const int d0 = (delta >> 2) & 1, d1 = (delta >> 1) & 1, d2 = delta & 1;
+      // position of this cell inside the halo of bin (tile - delta)
+      const int q0 = i0 + d0 * TILE, q1 = i1 + d1 * TILE, q2 = i2 + d2 * TILE;
+      hit[delta] = q0 < S && q1 < S && q2 < S && rng[2 * delta] < rng[2 * delta + 1];
+      off[delta] = ((int64_t)q0 * S + q1) * S + q2;
+    }
+    cx<T> first[8];
+#pragma unroll
+    for (int delta = 0; delta < 8; ++delta)
+      first[delta] = partials[hit[delta] ? rng[2 * delta] * SS + off[delta] : 0];
+#pragma unroll
+    for (int delta = 0; delta < 8; ++delta)
+      if (hit[delta]) acc = cadd(acc, first[delta]);
+#pragma unroll
+    for (int delta = 0; delta < 8; ++delta)
+      if (hit[delta])
+        for (int t = rng[2 * delta] + 1; t < rng[2 * delta + 1]; ++t)
+          acc = cadd(acc, partials[t * SS + off[delta]]);
+#else
 #pragma unroll
     for (int delta = 0; delta < 8; ++delta) {
       const int d0 = (delta >> 2) & 1, d1 = (delta >> 1) & 1, d2 = delta & 1;
@@ -509,6 +548,7 @@ __global__ __launch_bounds__(TILE * TILE * TILE < 1024 ? TILE * TILE * TILE : 10
           acc = cadd(acc, partials[t * SS + off]);
       }
     }
+#endif
     grid[((int64_t)(t0 * TILE + i0) * K + (t1 * TILE + i1)) * K + (t2 * TILE + i2)] = acc;
   }
 }
