@@ -24,6 +24,10 @@
 #include "fft_lds.h"
 #include "plan.h"
 
+#ifndef NUFFTCT_FFT_XCD_COLS
+#define NUFFTCT_FFT_XCD_COLS 1
+#endif
+
 namespace kfft {
 
 constexpr int NT = 256;
@@ -114,7 +118,17 @@ __global__ __launch_bounds__(NT) void k_fft_strided(cx<T>* __restrict__ grid,
   const int h = N / 2;
   const int o = blockIdx.y;
   const int qo = outer_pruned ? wrap_of(o - h, K) : o;
+#if NUFFTCT_FFT_XCD_COLS
+  // workgroups go round-robin over the 8 XCDs: give each XCD a contiguous
+  // run of column groups, so that the groups sharing a cache line of a row
+  // meet in one L2
+  int cg = blockIdx.x;
+  if ((gridDim.x & (NUFFTCT_NUM_XCD - 1)) == 0)
+    cg = (cg % NUFFTCT_NUM_XCD) * (gridDim.x / NUFFTCT_NUM_XCD) + cg / NUFFTCT_NUM_XCD;
+  const int col0 = cg * NL;
+#else
   const int col0 = blockIdx.x * NL;
+#endif
   cx<T>* base = grid + (int64_t)qo * outer_stride + col0;
   // squared distance of this block's nearest column from the ball's axis
   const double ko = outer_in_ball ? (double)(qo - K / 2) : 0.0;
