@@ -36,6 +36,9 @@ namespace kgrid {
 #ifndef NUFFTCT_INTERP_WAVES_PER_EU
 #define NUFFTCT_INTERP_WAVES_PER_EU 1
 #endif
+#ifndef NUFFTCT_SPREAD_RPI
+#define NUFFTCT_SPREAD_RPI 1
+#endif
 #ifndef NUFFTCT_MERGE_V2
 #define NUFFTCT_MERGE_V2 1
 #endif
@@ -128,6 +131,18 @@ __device__ __forceinline__ void axis_weights(const WeightPoly<T, DEG>& P, double
 }
 
 __device__ __forceinline__ int wrapK(int c, int K) { return c >= K ? c - K : c; }
+
+// floor(x + 1/2) as a 32-bit integer in one instruction (|x| < 2^31); the
+// compiler's round-to-nearest conversion takes two
+__device__ __forceinline__ int round_int(float x) {
+#if NUFFTCT_SPREAD_RPI
+  int r;
+  asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+#else
+  return __float2int_rn(x);
+#endif
+}
 
 // Innermost pitch of the interpolation's staged halo tile: for FP32, S rounded
 // up to even, so that a row's start parity equals its first tap's parity and
@@ -380,9 +395,11 @@ __attribute__((amdgpu_waves_per_eu(NUFFTCT_SPREAD_WAVES_PER_EU))) void k_spread(
           const cx<T> u =
               CW ? cmulc(vb, cx<T>{w2r[c], w2i[c]}) : cx<T>{w2r[c] * vb.x, w2r[c] * vb.y};
           if constexpr (FIXED) {
-            const long long qr = __float2int_rn(u.x), qi = __float2int_rn(u.y);
-            lds_add(&accp[row + c],
-                    ((unsigned long long)qr << 32) + (unsigned long long)qi);
+            // the word q_re 2^32 + q_im: low half q_im, high half q_re
+            // less the borrow of a negative q_im
+            const int qr = round_int(u.x), qi = round_int(u.y);
+            const unsigned int hi = (unsigned int)qr + (unsigned int)(qi >> 31);
+            lds_add(&accp[row + c], ((unsigned long long)hi << 32) | (unsigned int)qi);
           } else {
             lds_add(&acc[row + c], (double)u.x);
             lds_add(&acc[SS + row + c], (double)u.y);
