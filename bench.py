@@ -172,12 +172,87 @@ def cpu_oracle_baseline(x, dirs, n_r, N, K, J, sample_lines):
     return t, D, v
 
 
+def bench_batch(args):
+    """Batch of 64 volumes of uneven size (N in {48..160}, K = 2N, N_r = 2N,
+    N_phi even in [60, 240], N_theta = N_phi / 2): forward + adjoint of every
+    volume, captured once into two HIP graphs and replayed; metric = sum of
+    the volumes' points / time of one forward + adjoint replay."""
+    import numpy as np
+    import torch
+
+    import paper_1605_05231_amd as pkg
+    import synthetic
+
+    items = synthetic.batch_workload(64)
+    t0 = time.perf_counter()
+    vols = [w.volume() for w in items]
+    log(f"[bench] c5: {len(items)} volumes, N in {sorted(set(w.N for w in items))}, "
+        f"phantoms {time.perf_counter() - t0:.1f}s")
+    t0 = time.perf_counter()
+    batch = pkg.Batch([w.N for w in items], [w.K for w in items], 6,
+                      [w.directions() for w in items], [w.n_r for w in items])
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    Ms = batch.Ms
+    Mtot = int(sum(Ms))
+    log(f"[bench] c5: sum M = {Mtot}, batch plans {plan_s:.2f}s")
+    xs = [torch.from_numpy(v.astype(np.complex64)).cuda().reshape(-1) for v in vols]
+    ys = [torch.empty(m, dtype=torch.complex64, device="cuda") for m in Ms]
+    vs = [torch.empty(w.N ** 3, dtype=torch.complex64, device="cuda") for w in items]
+    st = torch.cuda.Stream()  # graph capture needs a non-default stream
+    with torch.cuda.stream(st):
+        # eager (stream-ordered launches) for comparison
+        for _ in range(args.warmup):
+            batch.forward(xs, ys)
+            batch.adjoint(ys, vs)
+        st.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            batch.forward(xs, ys)
+            batch.adjoint(ys, vs)
+        st.synchronize()
+        eager_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        batch.capture(0, xs, ys)
+        batch.capture(1, ys, vs)
+        for _ in range(args.warmup):
+            batch.replay(0)
+            batch.replay(1)
+        st.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for a, b in ev:
+            a.record(st)
+            batch.replay(0)
+            batch.replay(1)
+            b.record(st)
+        st.synchronize()
+        wall = time.perf_counter() - t0
+    per = sorted(a.elapsed_time(b) for a, b in ev)
+    ms = wall * 1e3 / args.steps
+    value = Mtot / (ms * 1e-3) / 1e6
+    log(f"[bench] c5 graph replay {ms:.3f} ms/step -> {value:.1f} Mpts/s (eager {eager_ms:.3f} ms)")
+    q = lambda f: round(per[min(len(per) - 1, int(f * len(per)))], 4)
+    print(json.dumps({
+        "metric": "fwd+adj NUFFT projector Mpts/s, batch of 64 uneven volumes (graph replay)",
+        "value": round(value, 2), "unit": "Mpts/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "c5: 64 volumes, N in {48, 64, 96, 128, 160}, K = 2N, J = 6 kb, "
+                               "N_phi x N_phi/2 lines x 2N samples", "points": Mtot,
+                   "step": "forward (derivative-Radon) + adjoint of every volume"},
+        "step_ms": {"p10": q(0.1), "median": q(0.5), "p90": q(0.9)},
+        "eager_ms_per_step": round(eager_ms, 4), "plan_s": round(plan_s, 2),
+    }), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c3", choices=["c2", "c3"])
+    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c5"],
+                    help="c5: batch of 64 uneven volumes, replayed from HIP graphs (own JSON line)")
     ap.add_argument("--kernel", default="kb", choices=["kb", "minmax"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
@@ -211,6 +286,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "c5":
+        bench_batch(args)
+        return
     W = synthetic.WORKLOADS[args.workload]
     N, K, J, n_r = W.N, W.K, W.J, W.n_r
     dirs = W.directions()
@@ -261,12 +339,20 @@ def main():
     plan.stage_times()  # clear
     plan.set_timing(True)
     torch.cuda.synchronize()
+    cur = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for a, b in ev:
+        a.record(cur)
         step()
+        b.record(cur)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     plan.set_timing(False)
+    per = sorted(a.elapsed_time(b) for a, b in ev)
+    step_ms = {"p10": round(per[int(0.1 * len(per))], 4), "median": round(per[len(per) // 2], 4),
+               "p90": round(per[min(len(per) - 1, int(0.9 * len(per)))], 4)}
     st = plan.stage_times()
     ms_per_step = wall * 1e3 / args.steps
     value = M / (ms_per_step * 1e-3) / 1e6
@@ -303,6 +389,7 @@ def main():
                    "N": N, "K": K, "J": J, "kernel": args.kernel, "points": M,
                    "step": "forward (derivative-Radon) + adjoint"},
         "roofline": roofline,
+        "step_ms": step_ms,
         "stages": stages,
         "touched_cells": touched,
         "plan_s": round(plan_s, 2),

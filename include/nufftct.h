@@ -184,12 +184,14 @@ int nufftct_get_stage_times(nufftct_plan* plan, double* ms, int64_t* count, int 
 
 /*
  * Batch of independent volumes of uneven size (each with its own radial
- * direction set), executed stage by stage so that one launch per stage
- * covers every volume of the same grid size, with the interpolation and
- * spreading of all volumes merged into one launch each.  The batch owns one
- * plan per volume (created with the given parameters; J, kernel, beta and
- * precision are shared).  Arrays are HOST arrays of length nvol; dirs[b] is
- * a HOST pointer to n_lines[b] x 3 doubles.
+ * direction set).  The batch owns one plan per volume (created with the
+ * given parameters; J, kernel, beta and precision are shared), each with its
+ * own workspace, so the volumes are independent: they are dealt to up to four
+ * worker streams (longest-processing-time order by estimated cost) that fork
+ * from the caller's stream and join back into it, so that small volumes run
+ * side by side.  Arrays are HOST arrays of length nvol; dirs[b] is a HOST
+ * pointer to n_lines[b] x 3 doubles.  Errors: EINVAL (a null array, nvol < 1,
+ * or any volume's plan parameters, reported with its index), ENOMEM, EHIP.
  */
 int nufftct_batch_create(nufftct_batch** out, int nvol, const int64_t* N, const int64_t* K,
                          int J, int kernel, double beta, int precision,
@@ -204,8 +206,10 @@ int nufftct_batch_adjoint(nufftct_batch* batch, const void* const* ins, void* co
 
 /*
  * Capture the batch's forward (dir = 0) or adjoint (dir = 1) for fixed
- * buffers into a HIP graph owned by the batch, and replay it with
- * nufftct_batch_graph_launch.  Replays read the same buffers given here.
+ * buffers into a HIP graph owned by the batch (the worker streams become
+ * parallel branches), and replay it with nufftct_batch_graph_launch.
+ * Replays read and write the same buffers given here.  The stream must not
+ * be NULL; stage timing is off inside the graph.
  */
 int nufftct_batch_graph_capture(nufftct_batch* batch, int dir, const void* const* src,
                                 void* const* dst, int flags, void* stream);

@@ -255,7 +255,9 @@ class Batch:
         else:
             a = self._ptrs(src, self.Ms, "y")
             b = self._ptrs(dst, [n ** 3 for n in self.Ns], "out")
-        self._keep = (src, dst)
+        # the graph holds raw pointers: keep each direction's buffers alive
+        self._keep = getattr(self, "_keep", {})
+        self._keep[direction] = (src, dst)
         _lib.check(_lib.load().nufftct_batch_graph_capture(self._ptr, direction, a, b,
                                                            RADIAL | (DERIV if deriv else 0),
                                                            C.c_void_p(_stream_handle(stream))))

@@ -1,16 +1,27 @@
-// Batches of independent volumes of uneven size: one plan per volume, driven
-// stage by stage on one stream, and HIP-graph capture/replay of a whole
-// batched forward or adjoint.
+// Batches of independent volumes of uneven size: one plan per volume (each
+// with its own workspace), the volumes spread over a few worker streams that
+// fork from and join back into the caller's stream, and HIP-graph
+// capture/replay of a whole batched forward or adjoint (the fork/join becomes
+// parallel branches of the graph).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <string>
 #include <vector>
 
 #include "plan.h"
 
+// worker streams per batch: small volumes leave most of the GPU idle, so a
+// few of them run side by side
+#define NUFFTCT_BATCH_LANES 4
+
 struct nufftct_batch {
   std::vector<nufftct_plan*> plans;
+  std::vector<int> lane_of;          // worker stream of each volume
+  std::vector<hipStream_t> lanes;    // default priority, non-blocking
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
   hipGraphExec_t exec[2] = {nullptr, nullptr};
   hipGraph_t graph[2] = {nullptr, nullptr};
 };
@@ -24,24 +35,60 @@ static void free_batch(nufftct_batch* b) {
     if (b->graph[d]) hipGraphDestroy(b->graph[d]);
   }
   for (auto* p : b->plans) nufftct_plan_destroy(p);
+  for (auto e : b->join) hipEventDestroy(e);
+  if (b->fork) hipEventDestroy(b->fork);
+  for (auto s : b->lanes) hipStreamDestroy(s);
   delete b;
 }
 
-// Run one direction over all volumes.  Volumes are visited grouped by grid
-// size so that consecutive launches reuse the same kernels.
+// Longest-processing-time assignment of volumes to lanes, by a cost of
+// K^3 log K (FFTs) plus M J^3 (interpolation or spreading).
+static void assign_lanes(nufftct_batch* b) {
+  const int n = (int)b->plans.size(), L = (int)b->lanes.size();
+  std::vector<double> cost(n), load(L, 0.0);
+  for (int i = 0; i < n; ++i) {
+    const nufftct_plan* p = b->plans[i];
+    const double K3 = (double)p->K * p->K * p->K;
+    cost[i] = K3 * std::log2((double)p->K) + (double)p->M * p->J * p->J * p->J;
+  }
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  b->lane_of.assign(n, 0);
+  for (int i : order) {
+    const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    b->lane_of[i] = l;
+    load[l] += cost[i];
+  }
+}
+
+// Run one direction over all volumes: fork the worker streams from the
+// caller's stream, run each volume on its lane, join them back.
 static int run_dir(nufftct_batch* b, int dir, const void* const* src, void* const* dst, int flags,
                    void* stream) {
-  std::vector<int> order(b->plans.size());
-  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int x, int y) { return b->plans[x]->K < b->plans[y]->K; });
-  for (int i : order) {
+  const int n = (int)b->plans.size();
+  for (int i = 0; i < n; ++i)
     if (!src[i] || !dst[i]) return bfail(NUFFTCT_EINVAL, "null buffer for volume " + std::to_string(i));
-    int rc = dir == 0 ? nufftct_forward(b->plans[i], src[i], dst[i], flags, stream)
-                      : nufftct_adjoint(b->plans[i], src[i], dst[i], flags, stream);
-    if (rc) return bfail(rc, "volume " + std::to_string(i) + ": " + nufftct_last_error());
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipEventRecord(b->fork, st);
+  for (size_t l = 0; l < b->lanes.size() && e == hipSuccess; ++l)
+    e = hipStreamWaitEvent(b->lanes[l], b->fork, 0);
+  if (e != hipSuccess) return bfail(NUFFTCT_EHIP, std::string("fork: ") + hipGetErrorString(e));
+  int rc = NUFFTCT_OK;
+  for (int i = 0; i < n && rc == NUFFTCT_OK; ++i) {
+    void* ls = (void*)b->lanes[b->lane_of[i]];
+    rc = dir == 0 ? nufftct_forward(b->plans[i], src[i], dst[i], flags, ls)
+                  : nufftct_adjoint(b->plans[i], src[i], dst[i], flags, ls);
+    if (rc) rc = bfail(rc, "volume " + std::to_string(i) + ": " + nufftct_last_error());
   }
-  return NUFFTCT_OK;
+  // join even after a failure, so that no lane is left forked (or capturing)
+  for (size_t l = 0; l < b->lanes.size(); ++l) {
+    hipError_t e1 = hipEventRecord(b->join[l], b->lanes[l]);
+    if (e1 == hipSuccess) e1 = hipStreamWaitEvent(st, b->join[l], 0);
+    if (e1 != hipSuccess && rc == NUFFTCT_OK)
+      rc = bfail(NUFFTCT_EHIP, std::string("join: ") + hipGetErrorString(e1));
+  }
+  return rc;
 }
 
 extern "C" {
@@ -66,6 +113,22 @@ int nufftct_batch_create(nufftct_batch** out, int nvol, const int64_t* N, const 
     }
     b->plans.push_back(p);
   }
+  const int L = std::min(nvol, NUFFTCT_BATCH_LANES);
+  hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+  for (int l = 0; l < L && e == hipSuccess; ++l) {
+    hipStream_t s = nullptr;
+    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) break;
+    b->lanes.push_back(s);
+    hipEvent_t ev = nullptr;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) b->join.push_back(ev);
+  }
+  if (e != hipSuccess) {
+    free_batch(b);
+    return bfail(NUFFTCT_EHIP, std::string("worker streams: ") + hipGetErrorString(e));
+  }
+  assign_lanes(b);
   *out = b;
   return NUFFTCT_OK;
 }

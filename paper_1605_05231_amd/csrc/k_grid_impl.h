@@ -39,9 +39,6 @@ namespace kgrid {
 #ifndef NUFFTCT_SPREAD_RPI
 #define NUFFTCT_SPREAD_RPI 1
 #endif
-#ifndef NUFFTCT_MERGE_V2
-#define NUFFTCT_MERGE_V2 1
-#endif
 constexpr int NT = 256;
 constexpr int NT_INTERP = NUFFTCT_INTERP_NT;
 #ifndef NUFFTCT_SPREAD_NT
@@ -113,6 +110,29 @@ template <typename T, int J, int DEG, bool CW>
 __device__ __forceinline__ void axis_weights(const WeightPoly<T, DEG>& P, double frac,
                                              T (&wr)[J], T (&wi)[J]) {
   const T z = (T)(2.0 * frac - 1.0);
+  if constexpr (!CW) {
+    // The Kaiser-Bessel kernel is even, so tap J-1-a at z is tap a at -z:
+    // with P_a(z) = E(z^2) + z O(z^2), w_a = E + z O and w_{J-1-a} = E - z O,
+    // half the polynomial work of evaluating every tap.
+    const T z2 = z * z;
+#pragma unroll
+    for (int a = 0; a < (J + 1) / 2; ++a) {
+      constexpr int TOPE = DEG & ~1, TOPO = (DEG - 1) | 1;  // highest even / odd power
+      T e = P.re[a][TOPE];
+#pragma unroll
+      for (int d = TOPE - 2; d >= 0; d -= 2) e = e * z2 + P.re[a][d];
+      T o = P.re[a][TOPO];
+#pragma unroll
+      for (int d = TOPO - 2; d >= 1; d -= 2) o = o * z2 + P.re[a][d];
+      wr[a] = e + z * o;
+      wi[a] = (T)0;
+      if (J - 1 - a != a) {  // (the middle tap of an odd J is its own mirror)
+        wr[J - 1 - a] = e - z * o;
+        wi[J - 1 - a] = (T)0;
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int a = 0; a < J; ++a) {
     T acc = P.re[a][DEG];
@@ -222,6 +242,36 @@ __device__ __forceinline__ cx<T> gather(const cx<T>* tile, const cx<T>* __restri
   return acc;
 }
 
+// Layout of a task's halo partial in memory.  The halo (S^3 cells, S = TILE +
+// R, R = J - 1) is cut per axis into the task's own TILE cells and the R cells
+// that belong to the next bin; the 8 resulting blocks are stored one after
+// another, block delta = 4 d0 + 2 d1 + d2 (d = 1: the outer part on that
+// axis), each row-major over its own extents.  Block delta is exactly what
+// bin (own + delta) adds to its cells [0, e0) x [0, e1) x [0, e2) (e = TILE or
+// R), so the merge reads every block as one contiguous, line-aligned run.
+// Per-task stride: S^3 rounded up to 16 cells (128 B for FP32).
+__host__ __device__ constexpr int part_ext(int d, int tile, int r) { return d ? r : tile; }
+__host__ __device__ constexpr int part_size(int delta, int tile, int r) {
+  return part_ext((delta >> 2) & 1, tile, r) * part_ext((delta >> 1) & 1, tile, r) *
+         part_ext(delta & 1, tile, r);
+}
+__host__ __device__ constexpr int part_base(int delta, int tile, int r) {
+  int b = 0;
+  for (int k = 0; k < delta; ++k) b += part_size(k, tile, r);
+  return b;
+}
+__host__ __device__ constexpr int part_stride(int tile, int r) {
+  return ((tile + r) * (tile + r) * (tile + r) + 15) / 16 * 16;
+}
+// offset in a task's partial of halo cell (q0, q1, q2)
+__host__ __device__ inline int part_offset(int q0, int q1, int q2, int tile, int r) {
+  const int d0 = q0 >= tile, d1 = q1 >= tile, d2 = q2 >= tile;
+  const int delta = 4 * d0 + 2 * d1 + d2;
+  const int e1 = part_ext(d1, tile, r), e2 = part_ext(d2, tile, r);
+  return part_base(delta, tile, r) + ((q0 - d0 * tile) * e1 + (q1 - d1 * tile)) * e2 +
+         (q2 - d2 * tile);
+}
+
 // ---------------------------------------------------------------------------
 template <typename T, int J, int TILE, bool CW, int DEG>
 __global__ __launch_bounds__(NT_INTERP)
@@ -304,7 +354,7 @@ __attribute__((amdgpu_waves_per_eu(NUFFTCT_INTERP_WAVES_PER_EU))) void k_interp(
 //     the task's scale s = 2^30 / (vmax B) (2^29 for complex weights), vmax
 //     the largest component of the task's inputs and B the plan-time bound on
 //     sum_points prod_axes |w| at any cell of the halo (k_spread_bound), every
-//     cell's sums of rounded contributions q = rn(s u) stay inside
+//     cell's sums of rounded contributions q = floor(s u + 1/2) stay inside
 //     [-2^31, 2^31).  Each tap adds the word q_re 2^32 + q_im (two's
 //     complement) with one ds_add_u64; the low half of a sum is then the sum
 //     of q_im and the rest the sum of q_re, the carries between them being
@@ -409,17 +459,30 @@ __attribute__((amdgpu_waves_per_eu(NUFFTCT_SPREAD_WAVES_PER_EU))) void k_spread(
     }
   }
   __syncthreads();
-  cx<T>* dst = partials + task_id * (int64_t)SS;
-  if constexpr (FIXED) {
-    const double inv = 1.0 / (double)scale;
-    for (int idx = threadIdx.x; idx < SS; idx += NT_SPREAD) {
-      const unsigned long long w = accp[idx];
-      const long long lo = (long long)(int)(unsigned int)(w & 0xffffffffull);
-      const long long hi = (long long)(w - (unsigned long long)lo) >> 32;
-      dst[idx] = cx<T>{(T)((double)hi * inv), (T)((double)lo * inv)};
+  // write the partial block by block (consecutive threads, consecutive
+  // addresses), see part_offset
+  constexpr int R = J - 1;
+  cx<T>* dst = partials + task_id * (int64_t)part_stride(TILE, R);
+  const double inv = 1.0 / (double)scale;
+#pragma unroll
+  for (int delta = 0; delta < 8; ++delta) {
+    const int d0 = (delta >> 2) & 1, d1 = (delta >> 1) & 1, d2 = delta & 1;
+    const int e1 = part_ext(d1, TILE, R), e2 = part_ext(d2, TILE, R);
+    const int n = part_size(delta, TILE, R), base = part_base(delta, TILE, R);
+    for (int idx = threadIdx.x; idx < n; idx += NT_SPREAD) {
+      const int r2 = idx % e2, r1 = (idx / e2) % e1, r0 = idx / (e1 * e2);
+      const int cell = ((r0 + d0 * TILE) * S + (r1 + d1 * TILE)) * S + (r2 + d2 * TILE);
+      cx<T> v;
+      if constexpr (FIXED) {
+        const unsigned long long w = accp[cell];
+        const long long lo = (long long)(int)(unsigned int)(w & 0xffffffffull);
+        const long long hi = (long long)(w - (unsigned long long)lo) >> 32;
+        v = cx<T>{(T)((double)hi * inv), (T)((double)lo * inv)};
+      } else {
+        v = cx<T>{(T)acc[cell], (T)acc[SS + cell]};
+      }
+      dst[base + idx] = v;
     }
-  } else {
-    for (int idx = threadIdx.x; idx < SS; idx += NT_SPREAD) dst[idx] = cx<T>{(T)acc[idx], (T)acc[SS + idx]};
   }
 }
 
@@ -490,15 +553,16 @@ __global__ __launch_bounds__(NT_SPREAD) void k_spread_bound(float* __restrict__ 
 // of the lower-neighbour bins whose halos reach it (J-1 cells into the tile).
 // One workgroup per tile and one thread per cell: the 8 source bins' task
 // ranges are read once per workgroup into LDS, then every cell issues its
-// (mostly single) partial loads independently.
+// (mostly single) partial loads independently.  With the block layout of the
+// partials, the cells of a row read consecutive words of each block.
 template <typename T, int TILE>
 __global__ __launch_bounds__(TILE * TILE * TILE < 1024 ? TILE * TILE * TILE : 1024) void k_merge(
     const cx<T>* __restrict__ partials, const int32_t* __restrict__ bin_tasks,
-    cx<T>* __restrict__ grid, int nb, int K, int S, double r2) {
+    cx<T>* __restrict__ grid, int nb, int K, int R, double r2) {
   constexpr int TT = TILE * TILE * TILE;
   constexpr int NTM = TT < 1024 ? TT : 1024;
   constexpr int PER = TT / NTM;
-  const int64_t SS = (int64_t)S * S * S;
+  const int64_t PS = part_stride(TILE, R);
   const int tile = (int)blockIdx.x;
   const int t2 = tile % nb, t1 = (tile / nb) % nb, t0 = tile / (nb * nb);
   {
@@ -527,7 +591,6 @@ __global__ __launch_bounds__(TILE * TILE * TILE < 1024 ? TILE * TILE * TILE : 10
     const int idx = (int)threadIdx.x + k * NTM;
     const int i2 = idx % TILE, i1 = (idx / TILE) % TILE, i0 = idx / (TILE * TILE);
     cx<T> acc = {0, 0};
-#if NUFFTCT_MERGE_V2
     // the first task of every source bin: eight independent loads (a source
     // that does not reach this cell reads a dummy word and adds zero), then
     // the further tasks of the bins that have several; a fixed order
@@ -536,15 +599,15 @@ __global__ __launch_bounds__(TILE * TILE * TILE < 1024 ? TILE * TILE * TILE : 10
 #pragma unroll
     for (int delta = 0; delta < 8; ++delta) {
       const int d0 = (delta >> 2) & 1, d1 = (delta >> 1) & 1, d2 = delta & 1;
-      // position of this cell inside the halo of bin (tile - delta)
-      const int q0 = i0 + d0 * TILE, q1 = i1 + d1 * TILE, q2 = i2 + d2 * TILE;
-      hit[delta] = q0 < S && q1 < S && q2 < S && rng[2 * delta] < rng[2 * delta + 1];
-      off[delta] = ((int64_t)q0 * S + q1) * S + q2;
+      // block delta of bin (tile - delta) covers cells [0,e0) x [0,e1) x [0,e2)
+      const int e0 = part_ext(d0, TILE, R), e1 = part_ext(d1, TILE, R), e2 = part_ext(d2, TILE, R);
+      hit[delta] = i0 < e0 && i1 < e1 && i2 < e2 && rng[2 * delta] < rng[2 * delta + 1];
+      off[delta] = part_base(delta, TILE, R) + (i0 * e1 + i1) * e2 + i2;
     }
     cx<T> first[8];
 #pragma unroll
     for (int delta = 0; delta < 8; ++delta)
-      first[delta] = partials[hit[delta] ? rng[2 * delta] * SS + off[delta] : 0];
+      first[delta] = partials[hit[delta] ? rng[2 * delta] * PS + off[delta] : 0];
 #pragma unroll
     for (int delta = 0; delta < 8; ++delta)
       if (hit[delta]) acc = cadd(acc, first[delta]);
@@ -552,20 +615,7 @@ __global__ __launch_bounds__(TILE * TILE * TILE < 1024 ? TILE * TILE * TILE : 10
     for (int delta = 0; delta < 8; ++delta)
       if (hit[delta])
         for (int t = rng[2 * delta] + 1; t < rng[2 * delta + 1]; ++t)
-          acc = cadd(acc, partials[t * SS + off[delta]]);
-#else
-#pragma unroll
-    for (int delta = 0; delta < 8; ++delta) {
-      const int d0 = (delta >> 2) & 1, d1 = (delta >> 1) & 1, d2 = delta & 1;
-      // position of this cell inside the halo of bin (tile - delta)
-      const int q0 = i0 + d0 * TILE, q1 = i1 + d1 * TILE, q2 = i2 + d2 * TILE;
-      if (q0 < S && q1 < S && q2 < S) {
-        const int64_t off = ((int64_t)q0 * S + q1) * S + q2;
-        for (int t = rng[2 * delta]; t < rng[2 * delta + 1]; ++t)
-          acc = cadd(acc, partials[t * SS + off]);
-      }
-    }
-#endif
+          acc = cadd(acc, partials[t * PS + off[delta]]);
     grid[((int64_t)(t0 * TILE + i0) * K + (t1 * TILE + i1)) * K + (t2 * TILE + i2)] = acc;
   }
 }
@@ -648,15 +698,15 @@ hipError_t run(const nufftct_plan& p, const void* src, void* dst, hipStream_t st
 
 template <typename T>
 hipError_t merge(const nufftct_plan& p, void* grid, hipStream_t st, bool prune) {
-  const int S = p.tile + p.J - 1;
+  const int R = p.J - 1;
   const double r2 = prune ? p.ball_r2 : 1e300;
   const dim3 grd((unsigned)((int64_t)p.nb * p.nb * p.nb));
   if (p.tile == 16)
     hipLaunchKernelGGL((k_merge<T, 16>), grd, dim3(1024), 0, st, (const cx<T>*)p.d_partials,
-                       p.d_bin_tasks, (cx<T>*)grid, p.nb, (int)p.K, S, r2);
+                       p.d_bin_tasks, (cx<T>*)grid, p.nb, (int)p.K, R, r2);
   else if (p.tile == 8)
     hipLaunchKernelGGL((k_merge<T, 8>), grd, dim3(512), 0, st, (const cx<T>*)p.d_partials,
-                       p.d_bin_tasks, (cx<T>*)grid, p.nb, (int)p.K, S, r2);
+                       p.d_bin_tasks, (cx<T>*)grid, p.nb, (int)p.K, R, r2);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -494,8 +494,11 @@ static int create(nufftct_plan** out, int64_t N, int64_t K, int J, int kernel, d
     if ((rc = upload((void**)&p->d_bin_tasks, B.bin_tasks.data(), B.bin_tasks.size(), st)))
       return bail(rc);
     const size_t cxb = precision == NUFFTCT_FP32 ? 8 : 16;
+    // per-task stride: the halo's S^3 cells rounded up to 16 (the merge's
+    // loads then start on 128-byte lines)
     const size_t S = (size_t)(p->tile + J - 1);
-    const size_t pbytes = (size_t)std::max<int64_t>(p->ntasks, 1) * S * S * S * cxb;
+    const size_t pstride = (S * S * S + 15) / 16 * 16;
+    const size_t pbytes = (size_t)std::max<int64_t>(p->ntasks, 1) * pstride * cxb;
     hipError_t e = hipMalloc(&p->d_partials, pbytes);
     if (e != hipSuccess) {
       free_plan(p);
