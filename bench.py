@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "fwd+adj NUFFT projector Mpts/s at 256³, rel-L2≤1e-4; FP32 vs FP64 form"
 HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 
 def log(*a):
@@ -49,11 +50,20 @@ def alg_bytes(N, K, M, cb, touched):
     }
 
 
+def alg_flops(M, J):
+    """Algorithmic FP32 flops per launch of the point kernels: per point, J^3
+    taps of a complex value times a real weight (2 FMA = 4 flop each), the
+    separable row and plane sums (2 FMA per row of J and per plane), and 3J
+    weight polynomials of degree 11 (11 FMA each)."""
+    per_point = 4 * J ** 3 + 4 * J * J + 4 * J + 3 * J * 11 * 2
+    return {"interp": per_point * M, "spread": per_point * M}
+
+
 # ---------------------------------------------------------------------------
 # rocprofv3 post-processing (summaries committed under profiles/)
 KERNEL_SOURCES = {"interp": "k_grid_impl.h", "spread": "k_grid_impl.h", "merge": "k_grid_impl.h",
                   "radial": "k_fft_impl.h", "radial_adj": "k_fft_impl.h"}
-KERNEL_NAMES = {"interp": "k_interp", "spread": "k_spread", "merge": "k_merge",
+KERNEL_NAMES = {"interp": "k_interp<", "spread": "k_spread<", "merge": "k_merge<",
                 "radial": "k_radial<float, 512, false>", "radial_adj": "k_radial<float, 512, true>"}
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "hbm_traffic_c3.json")
 
@@ -258,6 +268,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the tiling autotuner (defaults: tile 16, 4096 points per task)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-form comparison")
+    ap.add_argument("--tile", type=int, default=0, help="with --no-autotune: tile edge (8 or 16)")
+    ap.add_argument("--max-pts", type=int, default=0, help="with --no-autotune: points per task")
     ap.add_argument("--cpu-sample-lines", type=int, default=640)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (reference for HBM counters)")
@@ -299,7 +311,12 @@ def main():
     log(f"[bench] phantom {time.perf_counter() - t0:.1f}s")
 
     tune = None
-    if not args.no_autotune:
+    # explicit tiling (read by the library when a plan is created)
+    if args.tile:
+        os.environ["NUFFTCT_TILE"] = str(args.tile)
+    if args.max_pts:
+        os.environ["NUFFTCT_MAXPTS"] = str(args.max_pts)
+    if not args.no_autotune and not (args.tile or args.max_pts):
         t0 = time.perf_counter()
         tune = pkg.autotune(N, K, J, dirs, n_r, kernel=args.kernel)
         log(f"[bench] autotune {tune} in {time.perf_counter() - t0:.1f}s")
@@ -367,14 +384,27 @@ def main():
     touched = int(torch.count_nonzero(grid.real).item())
     del grid, ones
     ab = alg_bytes(N, K, M, 8, touched)
+    af = alg_flops(M, J)
     single = ["interp", "spread", "merge", "radial", "radial_adj"]
     dom = max(single, key=lambda k: stage_avg[k])
-    achieved = ab[dom] / (stage_avg[dom] * 1e-3) / 1e9
     tr = traffic_for(dom)
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None if tr is None else round(tr),
-                "alg_bytes_per_launch": ab[dom], "avg_launch_ms": round(stage_avg[dom], 4)}
+    if dom in af:
+        # interpolation / spreading: bound by on-chip arithmetic (VALU and LDS),
+        # priced against the FP32 vector peak
+        achieved = af[dom] / (stage_avg[dom] * 1e-3) / 1e12
+        roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 2),
+                    "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+                    "traffic": None if tr is None else round(tr),
+                    "alg_flops_per_launch": af[dom], "alg_bytes_per_launch": ab[dom],
+                    "hbm_frac": round(ab[dom] / (stage_avg[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    "avg_launch_ms": round(stage_avg[dom], 4)}
+    else:
+        achieved = ab[dom] / (stage_avg[dom] * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": None if tr is None else round(tr),
+                    "alg_bytes_per_launch": ab[dom], "avg_launch_ms": round(stage_avg[dom], 4)}
     stages = {k: {"avg_ms": round(stage_avg[k], 4),
                   "alg_GBps": round(ab[k] / (stage_avg[k] * 1e-3) / 1e9, 1) if stage_avg[k] and ab[k] else None}
               for k in stage_avg}
