@@ -72,8 +72,17 @@ __device__ __forceinline__ PtRaw fetch_point(const PointGeom& g, const int32_t* 
   PtRaw q;
   q.p = perm[idx];
   if (g.n_r) {
-    const int l = q.p / g.n_r;
-    const int c = q.p - l * g.n_r;
+    // line and sample of the point: q.p / n_r through a double reciprocal,
+    // corrected by one either way
+    int l = (int)((double)q.p * g.inv_nr);
+    int c = q.p - l * g.n_r;
+    if (c < 0) {
+      --l;
+      c += g.n_r;
+    } else if (c >= g.n_r) {
+      ++l;
+      c -= g.n_r;
+    }
     q.r = (double)(c - g.n_r / 2) * g.dr;
     q.a0 = g.dirs[3 * (int64_t)l + 0];
     q.a1 = g.dirs[3 * (int64_t)l + 1];
@@ -88,21 +97,41 @@ __device__ __forceinline__ PtRaw fetch_point(const PointGeom& g, const int32_t* 
 }
 
 // First tap (centred, wrapped to [0, K)) and fractional offset per axis, with
-// the host binning's FP64 arithmetic (no contraction).
+// the host binning's FP64 arithmetic (no contraction): t = omega / gamma,
+// k0 = floor(t - J/2).  FAST: t is first formed as omega * (1/gamma), which
+// differs from the quotient by a few ulps at most; where that leaves the
+// fractional part farther than 1e-9 from an integer, floor() cannot differ
+// and the result stands (the fraction then differs from the exact one by
+// ~1e-13, far below FP32 resolution); otherwise the exact quotient is taken.
+template <bool FAST>
 __device__ __forceinline__ void point_taps(const PointGeom& g, const PtRaw& q, int J,
                                            int (&first)[3], double (&frac)[3]) {
 #pragma clang fp contract(off)
   const double om[3] = {q.r * q.a0, q.r * q.a1, q.r * q.a2};
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const double t = om[d] / g.gamma;
-    const double tj = t - 0.5 * (double)J;
-    const double k0 = floor(tj);
+    double tj, k0;
+    bool exact = !FAST;
+    if (FAST) {
+      tj = om[d] * g.inv_gamma - 0.5 * (double)J;
+      k0 = floor(tj);
+      const double fr = tj - k0;
+      exact = fr < 1e-9 || fr > 1.0 - 1e-9;
+    }
+    if (exact) {
+      const double t = om[d] / g.gamma;
+      tj = t - 0.5 * (double)J;
+      k0 = floor(tj);
+    }
     frac[d] = tj - k0;
-    int64_t f = (int64_t)k0 + 1 + g.K / 2;
-    f %= g.K;
-    if (f < 0) f += g.K;
-    first[d] = (int)f;
+    // |omega| is bounded at plan creation, so k0 fits an int; wrap without a
+    // 64-bit modulo in the common case
+    int f = (int)k0 + 1 + g.K / 2;
+    if ((unsigned)f >= (unsigned)g.K) {
+      f %= g.K;
+      if (f < 0) f += g.K;
+    }
+    first[d] = f;
   }
 }
 
@@ -311,7 +340,7 @@ __attribute__((amdgpu_waves_per_eu(NUFFTCT_INTERP_WAVES_PER_EU))) void k_interp(
     const int p = cur.p;
     int first[3];
     double frac[3];
-    point_taps(g, cur, J, first, frac);
+    point_taps<sizeof(T) == 4>(g, cur, J, first, frac);
     T w0r[J], w0i[J], w1r[J], w1i[J], w2r[J], w2i[J];
     axis_weights<T, J, DEG, CW>(P, frac[0], w0r, w0i);
     axis_weights<T, J, DEG, CW>(P, frac[1], w1r, w1i);
@@ -420,7 +449,7 @@ __attribute__((amdgpu_waves_per_eu(NUFFTCT_SPREAD_WAVES_PER_EU))) void k_spread(
     v = cx<T>{v.x * scale, v.y * scale};
     int first[3];
     double frac[3];
-    point_taps(g, cur, J, first, frac);
+    point_taps<sizeof(T) == 4>(g, cur, J, first, frac);
     const int l0 = first[0] - o0, l1 = first[1] - o1, l2 = first[2] - o2;
     // the host bins with the same FP64 arithmetic, so every point of the task
     // lies in its tile; the check only keeps LDS accesses in bounds
@@ -512,7 +541,7 @@ __global__ __launch_bounds__(NT_SPREAD) void k_spread_bound(float* __restrict__ 
     const PtRaw cur = fetch_point(g, perm, tk.start + i);
     int first[3];
     double frac[3];
-    point_taps(g, cur, J, first, frac);
+    point_taps<sizeof(T) == 4>(g, cur, J, first, frac);
     const int l0 = first[0] - o0, l1 = first[1] - o1, l2 = first[2] - o2;
     if ((unsigned)l0 >= (unsigned)TILE || (unsigned)l1 >= (unsigned)TILE ||
         (unsigned)l2 >= (unsigned)TILE)

@@ -30,6 +30,8 @@ struct PointGeom {
   const double* pts;   // point plans: M x 3 omega values
   double dr;           // 2 pi / n_r (radial plans)
   double gamma;        // 2 pi / K
+  double inv_gamma;    // 1 / gamma, rounded once
+  double inv_nr;       // 1 / n_r (radial plans)
   int n_r;             // radial line length; 0 for point plans
   int K;
 };
@@ -90,6 +92,8 @@ struct nufftct_plan {
     g.pts = d_pts;
     g.dr = n_r ? (2.0 * M_PI) / (double)n_r : 0.0;
     g.gamma = (2.0 * M_PI) / (double)K;
+    g.inv_gamma = 1.0 / g.gamma;
+    g.inv_nr = n_r ? 1.0 / (double)n_r : 0.0;
     g.n_r = radial ? (int)n_r : 0;
     g.K = (int)K;
     return g;
