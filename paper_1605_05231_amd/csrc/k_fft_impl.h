@@ -30,7 +30,14 @@
 
 namespace kfft {
 
-constexpr int NT = 256;
+#ifndef NUFFTCT_FFT_LINE_NT
+#define NUFFTCT_FFT_LINE_NT 512
+#endif
+constexpr int NT = NUFFTCT_FFT_LINE_NT;  // threads of a line-major workgroup
+#ifndef NUFFTCT_FFT_STRIDED_NT
+#define NUFFTCT_FFT_STRIDED_NT 512
+#endif
+constexpr int NTS = NUFFTCT_FFT_STRIDED_NT;  // threads of a strided-pass workgroup
 
 template <typename T, int L>
 constexpr int nl_line() {  // lines per tile for line-major passes
@@ -105,7 +112,7 @@ __global__ __launch_bounds__(NT) void k_pad_fft_x(const cx<T>* __restrict__ vol,
 // ball = 2: load only such rows, the rest being zero (adjoint).  outer_in_ball
 // says whether the outer index is a transformed (centred) axis.
 template <typename T, int L, int S>
-__global__ __launch_bounds__(NT) void k_fft_strided(cx<T>* __restrict__ grid,
+__global__ __launch_bounds__(NTS) void k_fft_strided(cx<T>* __restrict__ grid,
                                                     const cx<T>* __restrict__ tw, int N,
                                                     int64_t row_stride, int64_t outer_stride,
                                                     int outer_pruned, int load_pruned,
@@ -140,7 +147,7 @@ __global__ __launch_bounds__(NT) void k_fft_strided(cx<T>* __restrict__ grid,
     // nothing of this block is ever needed; the adjoint still owes zeros to
     // the rows the next pass reads
     if (ball == 2) {
-      for (int idx = tid; idx < NL * L; idx += NT) {
+      for (int idx = tid; idx < NL * L; idx += NTS) {
         const int line = idx % NL, e = idx / NL;
         const int m = centred_of(e, K);
         if (!store_pruned || (m >= -h && m < h)) base[e * row_stride + line] = cx<T>{0, 0};
@@ -148,7 +155,7 @@ __global__ __launch_bounds__(NT) void k_fft_strided(cx<T>* __restrict__ grid,
     }
     return;
   }
-  for (int idx = tid; idx < NL * L; idx += NT) {
+  for (int idx = tid; idx < NL * L; idx += NTS) {
     const int line = idx % NL, e = idx / NL;
     cx<T> v = {0, 0};
     const int m = centred_of(e, K);
@@ -161,8 +168,8 @@ __global__ __launch_bounds__(NT) void k_fft_strided(cx<T>* __restrict__ grid,
     buf[idx] = v;  // column-major address e*NL + line
   }
   __syncthreads();
-  fft::run<T, L, NL, NT, false, S>(buf, tw, tid);
-  for (int idx = tid; idx < NL * L; idx += NT) {
+  fft::run<T, L, NL, NTS, false, S>(buf, tw, tid);
+  for (int idx = tid; idx < NL * L; idx += NTS) {
     const int line = idx % NL, e = idx / NL;
     const int m = centred_of(e, K);
     bool stv = !store_pruned || (m >= -h && m < h);
@@ -284,9 +291,9 @@ hipError_t pad_fft(const nufftct_plan& p, const void* vol, void* grid, hipStream
     const int64_t nlines = (int64_t)N * N;                                                    \
     hipLaunchKernelGGL((k_pad_fft_x<T, LL>), dim3((unsigned)((nlines + NLx - 1) / NLx)),      \
                        dim3(NT), 0, st, (const cx<T>*)vol, g, p.d_s, tw, N);                  \
-    hipLaunchKernelGGL((k_fft_strided<T, LL, -1>), dim3(LL / NLc, N), dim3(NT), 0, st, g, tw, \
+    hipLaunchKernelGGL((k_fft_strided<T, LL, -1>), dim3(LL / NLc, N), dim3(NTS), 0, st, g, tw, \
                        N, (int64_t)LL, (int64_t)LL * LL, 1, 1, 0, r2, ball, 0);              \
-    hipLaunchKernelGGL((k_fft_strided<T, LL, -1>), dim3(LL / NLc, LL), dim3(NT), 0, st, g,    \
+    hipLaunchKernelGGL((k_fft_strided<T, LL, -1>), dim3(LL / NLc, LL), dim3(NTS), 0, st, g,    \
                        tw, N, (int64_t)LL * LL, (int64_t)LL, 0, 1, 0, r2, ball, 1);          \
     return hipGetLastError();                                                                 \
   }
@@ -310,9 +317,9 @@ hipError_t ifft_crop(const nufftct_plan& p, void* grid, void* vol, hipStream_t s
     constexpr int NLx = nl_line<T, LL>();                                                     \
     constexpr int NLc = nl_col<T, LL>();                                                      \
     const int64_t nlines = (int64_t)N * N;                                                    \
-    hipLaunchKernelGGL((k_fft_strided<T, LL, +1>), dim3(LL / NLc, LL), dim3(NT), 0, st, g,    \
+    hipLaunchKernelGGL((k_fft_strided<T, LL, +1>), dim3(LL / NLc, LL), dim3(NTS), 0, st, g,    \
                        tw, N, (int64_t)LL * LL, (int64_t)LL, 0, 0, 1, r2, ball, 1);          \
-    hipLaunchKernelGGL((k_fft_strided<T, LL, +1>), dim3(LL / NLc, N), dim3(NT), 0, st, g, tw, \
+    hipLaunchKernelGGL((k_fft_strided<T, LL, +1>), dim3(LL / NLc, N), dim3(NTS), 0, st, g, tw, \
                        N, (int64_t)LL, (int64_t)LL * LL, 1, 0, 1, r2, ball, 0);              \
     hipLaunchKernelGGL((k_ifft_crop_x<T, LL>), dim3((unsigned)((nlines + NLx - 1) / NLx)),    \
                        dim3(NT), 0, st, (const cx<T>*)g, (cx<T>*)vol, p.d_s, tw, N);          \

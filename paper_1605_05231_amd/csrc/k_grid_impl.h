@@ -584,12 +584,19 @@ __global__ __launch_bounds__(NT_SPREAD) void k_spread_bound(float* __restrict__ 
 // ranges are read once per workgroup into LDS, then every cell issues its
 // (mostly single) partial loads independently.  With the block layout of the
 // partials, the cells of a row read consecutive words of each block.
+#ifndef NUFFTCT_MERGE_MASKED
+#define NUFFTCT_MERGE_MASKED 1
+#endif
+#ifndef NUFFTCT_MERGE_NT
+#define NUFFTCT_MERGE_NT 1024
+#endif
 template <typename T, int TILE>
-__global__ __launch_bounds__(TILE * TILE * TILE < 1024 ? TILE * TILE * TILE : 1024) void k_merge(
+__global__ __launch_bounds__(TILE * TILE * TILE < NUFFTCT_MERGE_NT ? TILE * TILE * TILE
+                                                                    : NUFFTCT_MERGE_NT) void k_merge(
     const cx<T>* __restrict__ partials, const int32_t* __restrict__ bin_tasks,
     cx<T>* __restrict__ grid, int nb, int K, int R, double r2) {
   constexpr int TT = TILE * TILE * TILE;
-  constexpr int NTM = TT < 1024 ? TT : 1024;
+  constexpr int NTM = TT < NUFFTCT_MERGE_NT ? TT : NUFFTCT_MERGE_NT;
   constexpr int PER = TT / NTM;
   const int64_t PS = part_stride(TILE, R);
   const int tile = (int)blockIdx.x;
@@ -620,9 +627,10 @@ __global__ __launch_bounds__(TILE * TILE * TILE < 1024 ? TILE * TILE * TILE : 10
     const int idx = (int)threadIdx.x + k * NTM;
     const int i2 = idx % TILE, i1 = (idx / TILE) % TILE, i0 = idx / (TILE * TILE);
     cx<T> acc = {0, 0};
-    // the first task of every source bin: eight independent loads (a source
-    // that does not reach this cell reads a dummy word and adds zero), then
-    // the further tasks of the bins that have several; a fixed order
+    // the first task of every source bin that reaches this cell: up to eight
+    // independent loads (lanes that miss a source do not load, and a wave
+    // whose lanes all miss skips it), then the further tasks of the bins that
+    // have several; a fixed order
     int64_t off[8];
     bool hit[8];
 #pragma unroll
@@ -635,8 +643,14 @@ __global__ __launch_bounds__(TILE * TILE * TILE < 1024 ? TILE * TILE * TILE : 10
     }
     cx<T> first[8];
 #pragma unroll
-    for (int delta = 0; delta < 8; ++delta)
+    for (int delta = 0; delta < 8; ++delta) {
+#if NUFFTCT_MERGE_MASKED
+      first[delta] = cx<T>{0, 0};
+      if (hit[delta]) first[delta] = partials[rng[2 * delta] * PS + off[delta]];
+#else
       first[delta] = partials[hit[delta] ? rng[2 * delta] * PS + off[delta] : 0];
+#endif
+    }
 #pragma unroll
     for (int delta = 0; delta < 8; ++delta)
       if (hit[delta]) acc = cadd(acc, first[delta]);
@@ -731,10 +745,10 @@ hipError_t merge(const nufftct_plan& p, void* grid, hipStream_t st, bool prune) 
   const double r2 = prune ? p.ball_r2 : 1e300;
   const dim3 grd((unsigned)((int64_t)p.nb * p.nb * p.nb));
   if (p.tile == 16)
-    hipLaunchKernelGGL((k_merge<T, 16>), grd, dim3(1024), 0, st, (const cx<T>*)p.d_partials,
+    hipLaunchKernelGGL((k_merge<T, 16>), grd, dim3(4096 < NUFFTCT_MERGE_NT ? 4096 : NUFFTCT_MERGE_NT), 0, st, (const cx<T>*)p.d_partials,
                        p.d_bin_tasks, (cx<T>*)grid, p.nb, (int)p.K, R, r2);
   else if (p.tile == 8)
-    hipLaunchKernelGGL((k_merge<T, 8>), grd, dim3(512), 0, st, (const cx<T>*)p.d_partials,
+    hipLaunchKernelGGL((k_merge<T, 8>), grd, dim3(512 < NUFFTCT_MERGE_NT ? 512 : NUFFTCT_MERGE_NT), 0, st, (const cx<T>*)p.d_partials,
                        p.d_bin_tasks, (cx<T>*)grid, p.nb, (int)p.K, R, r2);
   else
     return hipErrorInvalidValue;
