@@ -14,6 +14,8 @@ Modules
              Fourier-slice samples into derivative-Radon values (Section 2.2.1,
              eq 2.17-2.18) and its adjoint
   projector  the composition image -> radially sampled derivative-Radon space
+  recon      direct reconstruction from derivative-Radon data: the 3D ramp
+             and the NUFFT transpose with angular quadrature (Section 2.3)
   complexity the paper's multiplication-count model (Section 2.4, eq 2.16-2.27)
 
 Conventions (where the paper is silent these are readings, not quotations):
@@ -30,4 +32,4 @@ Parity status of each function is stated in its docstring; every function is
 pinned by the tests in tests/test_oracle_*.py.
 """
 
-from . import nudft, kernels, nufft, radial, projector, complexity  # noqa: F401
+from . import nudft, kernels, nufft, radial, projector, recon, complexity  # noqa: F401
