@@ -256,13 +256,85 @@ def bench_batch(args):
     }), flush=True)
 
 
+def bench_recon(args):
+    """Direct reconstruction (ramp + NUFFT transpose with angular quadrature):
+    its speed at c3 (Mpts/s = M / time of one reconstruction from resident
+    derivative-Radon data), then the angular-sampling experiment: a 64^3
+    ellipsoid phantom projected on N_phi x N_phi/2 lines of 128 samples and
+    reconstructed, error against the phantom as N_phi grows."""
+    import numpy as np
+    import torch
+
+    import paper_1605_05231_amd as pkg
+    import synthetic
+
+    W = synthetic.WORKLOADS["c3"]
+    N, K, J, n_r = W.N, W.K, W.J, W.n_r
+    dirs = W.directions()
+    M = W.M
+    phi = synthetic.azimuths(W.n_phi)
+    th = synthetic.polar_angles(W.n_theta)
+    plan = pkg.Plan(N, K, J, dirs=dirs, n_r=n_r, dtype=torch.complex64)
+    plan.set_line_weights(pkg.radial_quadrature(phi, th))
+    x = torch.from_numpy(W.volume().astype(np.complex64)).cuda()
+    d = plan.forward(x)
+    v = torch.empty_like(x)
+    for _ in range(args.warmup):
+        plan.reconstruct(d, out=v)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.reconstruct(d, out=v)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    xn = x.real.cpu().numpy()
+    vr = v.real.cpu().numpy()
+    err_c3 = float(np.linalg.norm(vr - xn) / np.linalg.norm(xn))
+    log(f"[bench] e1: c3 reconstruction {ms:.3f} ms -> {M / (ms * 1e-3) / 1e6:.1f} Mpts/s, "
+        f"rel-L2 vs phantom {err_c3:.3e}")
+    del plan, x, d, v
+    torch.cuda.empty_cache()
+
+    # angular-sampling experiment (Section 3.1, here in 3D): error vs lines
+    Ne, ne_r = 64, 128
+    xe = synthetic.ellipsoid_phantom(Ne, 20, 3100)
+    xt = torch.from_numpy(xe.astype(np.complex64)).cuda()
+    curve = []
+    for n_phi in (16, 24, 32, 48, 64, 96, 128, 160, 200, 256):
+        ph = synthetic.azimuths(n_phi)
+        tt = synthetic.polar_angles(n_phi // 2)
+        dr = synthetic.line_directions(ph, tt)
+        p = pkg.Plan(Ne, 2 * Ne, 6, dirs=dr, n_r=ne_r, dtype=torch.complex64)
+        p.set_line_weights(pkg.radial_quadrature(ph, tt))
+        rec = p.reconstruct(p.forward(xt)).real.cpu().numpy()
+        mean_abs = float(np.mean(np.abs(rec - xe)))
+        rel = float(np.linalg.norm(rec - xe) / np.linalg.norm(xe))
+        curve.append({"n_phi": n_phi, "n_theta": n_phi // 2, "lines": len(dr),
+                      "mean_abs_err_per_voxel": mean_abs, "rel_l2": rel})
+        log(f"[bench] e1: N_phi {n_phi:4d} lines {len(dr):6d}: mean |err| {mean_abs:.4e}, rel-L2 {rel:.4e}")
+        p.close()
+    print(json.dumps({
+        "metric": "direct reconstruction (ramp + NUFFT transpose) Mpts/s at 256³",
+        "value": round(M / (ms * 1e-3) / 1e6, 2), "unit": "Mpts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "c3 reconstruction from its own derivative-Radon data; "
+                               "angular sampling experiment: 64^3 phantom, N_phi x N_phi/2 lines x 128",
+                   "points": M},
+        "c3_rel_l2_vs_phantom": err_c3,
+        "angular_sampling": curve,
+    }), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c5"],
-                    help="c5: batch of 64 uneven volumes, replayed from HIP graphs (own JSON line)")
+    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c5", "e1"],
+                    help="c5: batch of 64 uneven volumes, replayed from HIP graphs; e1: direct "
+                         "reconstruction at c3 and the angular-sampling experiment (own JSON lines)")
     ap.add_argument("--kernel", default="kb", choices=["kb", "minmax"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
@@ -300,6 +372,9 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "c5":
         bench_batch(args)
+        return
+    if args.workload == "e1":
+        bench_recon(args)
         return
     W = synthetic.WORKLOADS[args.workload]
     N, K, J, n_r = W.N, W.K, W.J, W.n_r

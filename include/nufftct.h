@@ -152,6 +152,40 @@ int nufftct_forward(nufftct_plan* plan, const void* vol, void* out, int flags, v
 int nufftct_adjoint(nufftct_plan* plan, const void* in, void* vol, int flags, void* stream);
 
 /*
+ * Direct reconstruction from radially sampled first-derivative Radon data
+ * (Section 2.3: the image -> Radon step inverted by a Fourier-domain ramp
+ * filter and the NUFFT transpose; the Introduction's R^2 ramp of the 3D
+ * parallel geometry).  With the 3D inverse Fourier transform written over
+ * whole lines through the origin, every direction of the sphere taken once,
+ *     x(m) = 1/(2 (2 pi)^3) int_{S^2} int r^2 X(r n) exp(i r n.m) dr dOmega,
+ * the ramp r^2 is conj(f_c) f_c of the derivative factor, so
+ *     vol = 1/(8 pi^2) * A^H diag(w) in,
+ * A^H the adjoint with NUFFTCT_DERIV_RADIAL and w the per-line quadrature
+ * weights of the directions (set with nufftct_set_line_weights).
+ *
+ * nufftct_radial_quadrature: weights for a product grid of azimuths phi
+ * (periodic, any order of increasing values) and increasing polar angles
+ * theta, lines ordered [phi][theta] (the layout of the radial directions):
+ * w[a*n_theta + b] = dphi_a * dtheta_b * sin(theta_b), dphi_a half the
+ * periodic distance between phi_a's neighbours, dtheta_b the trapezoid
+ * weight on [theta_0, theta_last] (2 for a single polar angle).  HOST arrays
+ * (w: n_phi * n_theta doubles, caller-owned); no device work.  Errors: EINVAL
+ * (NULL array, a count < 1, non-finite values, theta not increasing).
+ *
+ * nufftct_set_line_weights: copies n_lines HOST doubles into the plan
+ * (blocking; the plan owns the copy).  EINVAL: NULL, non-radial plan,
+ * non-finite weight; ENOMEM.
+ *
+ * nufftct_reconstruct: in (device, M complex derivative-Radon values, line
+ * order) -> vol (device, N^3 complex, overwritten); stream-ordered.  EINVAL:
+ * NULL or aliasing buffers, non-radial plan, no weights set.
+ */
+int nufftct_radial_quadrature(const double* phi, int64_t n_phi, const double* theta,
+                              int64_t n_theta, double* w);
+int nufftct_set_line_weights(nufftct_plan* plan, const double* w, void* stream);
+int nufftct_reconstruct(nufftct_plan* plan, const void* in, void* vol, void* stream);
+
+/*
  * Run one stage of the path (NUFFTCT_STAGE_*) from `in` to `out` (device
  * pointers of the sizes listed with each stage).  STAGE_SPREAD overwrites all
  * K^3 cells of `out`.  Used by the stage-parity tests and by profiling.

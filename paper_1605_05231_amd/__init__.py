@@ -17,7 +17,8 @@ from ._lib import (DERIV, DERIV_RADIAL, FP32, FP64, KERNEL_KB, KERNEL_MINMAX_KB,
                    STAGE_IFFT_CROP, STAGE_INTERP, STAGE_NAMES, STAGE_PAD_FFT, STAGE_RADIAL,
                    STAGE_RADIAL_ADJ, STAGE_SPREAD, NufftError)
 
-__all__ = ["Plan", "Batch", "NufftProjector", "project", "autotune", "NufftError", "version"]
+__all__ = ["Plan", "Batch", "NufftProjector", "project", "autotune", "radial_quadrature", "NufftError",
+           "version"]
 
 
 def _torch():
@@ -153,6 +154,26 @@ class Plan:
                                                C.c_void_p(_stream_handle(stream))))
         return out
 
+    def set_line_weights(self, w):
+        """Per-line quadrature weights (n_lines values) for `reconstruct`."""
+        w = np.ascontiguousarray(np.asarray(w, dtype=np.float64).reshape(-1))
+        if self.n_r == 0 or w.shape[0] != self.M // self.n_r:
+            raise ValueError(f"need one weight per line ({self.M // max(self.n_r, 1)}), got {w.shape[0]}")
+        _lib.check(_lib.load().nufftct_set_line_weights(self._ptr, w.ctypes.data_as(C.POINTER(C.c_double)),
+                                                        C.c_void_p(_stream_handle())))
+
+    def reconstruct(self, d, out=None, *, stream=None):
+        """Direct reconstruction 1/(8 pi^2) A^H diag(w) d from derivative-Radon
+        values d ((L, n_r) or (M,)) with the weights of `set_line_weights`."""
+        torch = _torch()
+        _check_tensor(d, self.M, self.dtype, "d")
+        if out is None:
+            out = torch.empty(self.vol_shape, dtype=self.dtype, device=d.device)
+        _check_tensor(out, self.N ** 3, self.dtype, "out")
+        _lib.check(_lib.load().nufftct_reconstruct(self._ptr, d.data_ptr(), out.data_ptr(),
+                                                   C.c_void_p(_stream_handle(stream))))
+        return out
+
     def stage(self, stage: int, inp, out, *, deriv: bool = True, stream=None):
         """Run a single stage (STAGE_*); sizes: vol N^3, grid K^3, points M."""
         sizes = {STAGE_PAD_FFT: (self.N ** 3, self.K ** 3), STAGE_INTERP: (self.K ** 3, self.M),
@@ -192,6 +213,19 @@ def autotune(N: int, K: int, J: int, dirs, n_r: int, *, kernel: str = "kb", beta
         d.shape[0], int(n_r), RADIAL | (DERIV if deriv else 0), C.byref(t), C.byref(m), C.byref(ms),
         C.c_void_p(_stream_handle())))
     return {"tile": t.value, "max_pts": m.value, "ms": ms.value}
+
+
+def radial_quadrature(phi, theta) -> np.ndarray:
+    """Quadrature weights of the directions of a (phi, theta) line grid, lines
+    ordered [phi][theta] (computed by the library on the host)."""
+    phi = np.ascontiguousarray(np.asarray(phi, dtype=np.float64).reshape(-1))
+    theta = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1))
+    w = np.empty(len(phi) * len(theta), dtype=np.float64)
+    dp = C.POINTER(C.c_double)
+    _lib.check(_lib.load().nufftct_radial_quadrature(phi.ctypes.data_as(dp), len(phi),
+                                                     theta.ctypes.data_as(dp), len(theta),
+                                                     w.ctypes.data_as(dp)))
+    return w
 
 
 class Batch:

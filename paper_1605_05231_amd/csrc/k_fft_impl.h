@@ -234,7 +234,9 @@ template <typename T, int L, bool ADJ>
 __global__ __launch_bounds__(NT) void k_radial(const cx<T>* __restrict__ in,
                                                cx<T>* __restrict__ out,
                                                const cx<T>* __restrict__ tw, int64_t nlines,
-                                               int deriv, double dr) {
+                                               int deriv, double dr,
+                                               const double* __restrict__ line_w,
+                                               double w_scale) {
   constexpr int NL = nl_line<T, L>();
   __shared__ cx<T> buf[fft::tile_elems<true, L, NL>()];
   const int tid = threadIdx.x;
@@ -261,7 +263,10 @@ __global__ __launch_bounds__(NT) void k_radial(const cx<T>* __restrict__ in,
     const int64_t gl = line0 + line;
     if (gl < nlines) {
       cx<T> v = buf[fft::addr<true, L, NL>(line, e)];
-      const T sc = (e & 1) ? -post : post;
+      T sc = (e & 1) ? -post : post;
+      // adjoint with per-line weights (the direct reconstruction): the line's
+      // weight times the reconstruction constant, rounded once
+      if (ADJ && line_w) sc *= (T)(line_w[gl] * w_scale);
       v = cx<T>{v.x * sc, v.y * sc};
       if (ADJ && deriv) {  // multiply by conj(f_c) = -i r_c, f_0 = 0
         const T r = e == 0 ? (T)0 : (T)((double)(e - L / 2) * dr);
@@ -334,7 +339,7 @@ hipError_t ifft_crop(const nufftct_plan& p, void* grid, void* vol, hipStream_t s
 
 template <typename T>
 hipError_t radial(const nufftct_plan& p, const void* in, void* out, bool adj, bool deriv,
-                  hipStream_t st) {
+                  hipStream_t st, const double* line_w, double w_scale) {
   const int64_t nl = p.M / p.n_r;
   const cx<T>* tw = (const cx<T>*)p.d_tw_r;
   const double dr = (2.0 * M_PI) / (double)p.n_r;
@@ -345,10 +350,10 @@ hipError_t radial(const nufftct_plan& p, const void* in, void* out, bool adj, bo
     dim3 grd((unsigned)((nl + NLx - 1) / NLx));                                                \
     if (adj)                                                                                   \
       hipLaunchKernelGGL((k_radial<T, LL, true>), grd, dim3(NT), 0, st, (const cx<T>*)in,      \
-                         (cx<T>*)out, tw, nl, (int)deriv, dr);                                 \
+                         (cx<T>*)out, tw, nl, (int)deriv, dr, line_w, w_scale);                \
     else                                                                                       \
       hipLaunchKernelGGL((k_radial<T, LL, false>), grd, dim3(NT), 0, st, (const cx<T>*)in,     \
-                         (cx<T>*)out, tw, nl, (int)deriv, dr);                                 \
+                         (cx<T>*)out, tw, nl, (int)deriv, dr, nullptr, 1.0);                   \
     return hipGetLastError();                                                                  \
   }
     KFFT_SIZES(CASE)
@@ -373,6 +378,7 @@ hipError_t radial(const nufftct_plan& p, const void* in, void* out, bool adj, bo
   }                                                                                        \
   template <>                                                                              \
   hipError_t launch_radial<T>(const nufftct_plan& p, const void* in, void* out, bool adj,  \
-                              bool deriv, hipStream_t s) {                                 \
-    return kfft::radial<T>(p, in, out, adj, deriv, s);                                     \
+                              bool deriv, hipStream_t s, const double* line_w,             \
+                              double w_scale) {                                            \
+    return kfft::radial<T>(p, in, out, adj, deriv, s, line_w, w_scale);                    \
   }

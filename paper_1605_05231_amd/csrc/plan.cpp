@@ -221,6 +221,7 @@ static void free_plan(nufftct_plan* p) {
   hipFree(p->d_bin_tasks);
   hipFree(p->d_partials);
   hipFree(p->d_bound);
+  hipFree(p->d_line_w);
   hipFree(p->d_grid);
   hipFree(p->d_tmp);
   for (auto& e : p->events) {
@@ -581,6 +582,13 @@ struct StageTimer {
 
 // prune: grid cells outside the taps' ball are neither produced nor read
 // (the operator paths); the single-stage entry point works on full grids
+// internal flag (never accepted from callers): the adjoint radial stage scales
+// line l by w_l / (8 pi^2), the direct reconstruction of Section 2.3
+constexpr int FLAG_LINE_WEIGHTS = 1 << 16;
+// 3D inverse Fourier transform in spherical coordinates over whole lines,
+// with the radial sum's 2 pi: 1 / (2 (2 pi)^3) * 2 pi
+constexpr double RECON_SCALE = 1.0 / (8.0 * M_PI * M_PI);
+
 template <typename T>
 static hipError_t run_stage(nufftct_plan* p, int stage, const void* in, void* out, int flags,
                             hipStream_t st, bool prune) {
@@ -597,7 +605,8 @@ static hipError_t run_stage(nufftct_plan* p, int stage, const void* in, void* ou
       e = launch_radial<T>(*p, in, out, false, (flags & NUFFTCT_DERIV) != 0, st);
       break;
     case NUFFTCT_STAGE_RADIAL_ADJ:
-      e = launch_radial<T>(*p, in, out, true, (flags & NUFFTCT_DERIV) != 0, st);
+      e = launch_radial<T>(*p, in, out, true, (flags & NUFFTCT_DERIV) != 0, st,
+                           (flags & FLAG_LINE_WEIGHTS) ? p->d_line_w : nullptr, RECON_SCALE);
       break;
     case NUFFTCT_STAGE_SPREAD: {
       // halo partials per task, then the owner-computes merge writes every
@@ -766,6 +775,73 @@ int nufftct_adjoint(nufftct_plan* p, const void* in, void* vol, int flags, void*
   int rc = check_call(p, in, vol, flags);
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
+  return p->precision == NUFFTCT_FP32 ? adjoint_impl<float>(p, in, vol, flags, st)
+                                      : adjoint_impl<double>(p, in, vol, flags, st);
+}
+
+int nufftct_radial_quadrature(const double* phi, int64_t n_phi, const double* theta,
+                              int64_t n_theta, double* w) {
+  if (!phi || !theta || !w) return fail(NUFFTCT_EINVAL, "null array");
+  if (n_phi < 1 || n_theta < 1) return fail(NUFFTCT_EINVAL, "n_phi and n_theta must be >= 1");
+  for (int64_t i = 0; i < n_phi; ++i)
+    if (!std::isfinite(phi[i])) return fail(NUFFTCT_EINVAL, "phi must be finite");
+  for (int64_t i = 0; i < n_theta; ++i)
+    if (!std::isfinite(theta[i])) return fail(NUFFTCT_EINVAL, "theta must be finite");
+  for (int64_t i = 1; i < n_theta; ++i)
+    if (!(theta[i] > theta[i - 1])) return fail(NUFFTCT_EINVAL, "theta must increase");
+  const double tau = 2.0 * M_PI;
+  auto wrap = [&](double v) {  // into [0, 2 pi)
+    v = std::fmod(v, tau);
+    return v < 0 ? v + tau : v;
+  };
+  for (int64_t a = 0; a < n_phi; ++a) {
+    // periodic midpoint spacing: half the way to each neighbour
+    double da = tau;
+    if (n_phi > 1) {
+      const double next = phi[(a + 1) % n_phi], prev = phi[(a + n_phi - 1) % n_phi];
+      da = 0.5 * (wrap(next - phi[a]) + wrap(phi[a] - prev));
+    }
+    for (int64_t b = 0; b < n_theta; ++b) {
+      // trapezoid rule in theta over [theta_0, theta_last]
+      double db = 2.0;  // one polar angle: the sine integral of the whole sphere
+      if (n_theta > 1) {
+        db = 0.0;
+        if (b > 0) db += 0.5 * (theta[b] - theta[b - 1]);
+        if (b + 1 < n_theta) db += 0.5 * (theta[b + 1] - theta[b]);
+      }
+      w[a * n_theta + b] = da * db * std::sin(theta[b]);
+    }
+  }
+  g_err.clear();
+  return NUFFTCT_OK;
+}
+
+int nufftct_set_line_weights(nufftct_plan* p, const double* w, void* stream) {
+  if (!p) return fail(NUFFTCT_EINVAL, "plan is NULL");
+  if (!w) return fail(NUFFTCT_EINVAL, "weights are NULL");
+  if (p->n_r == 0 || p->n_lines < 1) return fail(NUFFTCT_EINVAL, "plan has no radial lines (n_r = 0)");
+  for (int64_t l = 0; l < p->n_lines; ++l)
+    if (!std::isfinite(w[l])) return fail(NUFFTCT_EINVAL, "weight of line %lld is not finite", (long long)l);
+  hipStream_t st = (hipStream_t)stream;
+  if (!p->d_line_w) {
+    hipError_t e = hipMalloc(&p->d_line_w, (size_t)p->n_lines * sizeof(double));
+    if (e != hipSuccess) {
+      p->d_line_w = nullptr;
+      return fail(NUFFTCT_ENOMEM, "line weights: %s", hipGetErrorString(e));
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(p->d_line_w, w, (size_t)p->n_lines * sizeof(double), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  g_err.clear();
+  return NUFFTCT_OK;
+}
+
+int nufftct_reconstruct(nufftct_plan* p, const void* in, void* vol, void* stream) {
+  int rc = check_call(p, in, vol, NUFFTCT_DERIV_RADIAL);
+  if (rc) return rc;
+  if (!p->d_line_w) return fail(NUFFTCT_EINVAL, "no line weights set (nufftct_set_line_weights)");
+  hipStream_t st = (hipStream_t)stream;
+  const int flags = NUFFTCT_DERIV_RADIAL | FLAG_LINE_WEIGHTS;
   return p->precision == NUFFTCT_FP32 ? adjoint_impl<float>(p, in, vol, flags, st)
                                       : adjoint_impl<double>(p, in, vol, flags, st);
 }

@@ -71,6 +71,7 @@ struct nufftct_plan {
   int32_t* d_bin_tasks = nullptr;  // nb^3 + 1 offsets: tasks of bin b are [o[b], o[b+1])
   void* d_partials = nullptr;      // per task, its spread halo tile (S^3 complex)
   float* d_bound = nullptr;        // FP32: per task, max over halo cells of sum |w|
+  double* d_line_w = nullptr;      // radial plans: per-line reconstruction weights (optional)
   void* d_grid = nullptr;       // K^3 complex workspace
   void* d_tmp = nullptr;        // M complex workspace
   size_t grid_bytes = 0, tmp_bytes = 0, partial_bytes = 0;
@@ -111,8 +112,11 @@ template <typename T>
 hipError_t launch_ifft_crop(const nufftct_plan& p, void* grid, void* vol, hipStream_t s,
                             bool prune);
 template <typename T>
+// line_w (device, one weight per line, or NULL) scales the adjoint's output
+// lines by line_w[l] * w_scale
 hipError_t launch_radial(const nufftct_plan& p, const void* in, void* out, bool adjoint,
-                         bool deriv, hipStream_t s);
+                         bool deriv, hipStream_t s, const double* line_w = nullptr,
+                         double w_scale = 1.0);
 // interpolation / spreading (k_grid.hip)
 template <typename T>
 hipError_t launch_interp(const nufftct_plan& p, const void* grid, void* out, hipStream_t s);

@@ -1,6 +1,7 @@
 """Host-only checks of the C ABI: the library loads, exports every declared
 symbol, and rejects bad arguments before touching a GPU."""
 import ctypes as C
+import math
 import os
 import re
 
@@ -91,3 +92,36 @@ def test_valid_plan_without_device_fails_cleanly():
     rc, p, msg = _radial()
     assert rc in (_lib.EHIP, _lib.ENOMEM) and msg
     assert p.value is None
+
+
+def test_radial_quadrature_matches_oracle():
+    # host-only library routine (no device work) against the oracle's own weights
+    from oracle import recon
+    import synthetic
+    lib = _lib.load()
+    dp = C.POINTER(C.c_double)
+    for n_phi, margin in ((12, 0.2), (7, 0.0), (1, 0.3)):
+        phi = np.ascontiguousarray(synthetic.azimuths(n_phi))
+        for n_th in (1, 2, 9):
+            th = np.ascontiguousarray(synthetic.polar_angles(n_th, margin=margin)) if n_th > 1 \
+                else np.array([math.pi / 2])
+            w = np.empty(n_phi * n_th)
+            rc = lib.nufftct_radial_quadrature(phi.ctypes.data_as(dp), n_phi, th.ctypes.data_as(dp),
+                                               n_th, w.ctypes.data_as(dp))
+            assert rc == _lib.OK
+            want = recon.quadrature(phi, th)
+            assert np.max(np.abs(w - want)) <= 1e-14 * np.max(np.abs(want)), (n_phi, n_th)
+
+
+def test_reconstruction_entry_points_reject_bad_arguments():
+    lib = _lib.load()
+    dp = C.POINTER(C.c_double)
+    phi = np.array([0.0, 1.0])
+    th = np.array([1.0, 0.5])  # not increasing
+    w = np.empty(4)
+    assert lib.nufftct_radial_quadrature(phi.ctypes.data_as(dp), 2, th.ctypes.data_as(dp), 2,
+                                         w.ctypes.data_as(dp)) == _lib.EINVAL
+    assert lib.nufftct_radial_quadrature(None, 2, th.ctypes.data_as(dp), 2,
+                                         w.ctypes.data_as(dp)) == _lib.EINVAL
+    assert lib.nufftct_set_line_weights(None, w.ctypes.data_as(dp), None) == _lib.EINVAL
+    assert lib.nufftct_reconstruct(None, C.c_void_p(16), C.c_void_p(32), None) == _lib.EINVAL
