@@ -35,7 +35,7 @@ namespace kfft {
 #endif
 constexpr int NT = NUFFTCT_FFT_LINE_NT;  // threads of a line-major workgroup
 #ifndef NUFFTCT_FFT_STRIDED_NT
-#define NUFFTCT_FFT_STRIDED_NT 512
+#define NUFFTCT_FFT_STRIDED_NT 1024
 #endif
 constexpr int NTS = NUFFTCT_FFT_STRIDED_NT;  // threads of a strided-pass workgroup
 
@@ -46,7 +46,7 @@ constexpr int nl_line() {  // lines per tile for line-major passes
 }
 
 #ifndef NUFFTCT_FFT_COLS_F32
-#define NUFFTCT_FFT_COLS_F32 8
+#define NUFFTCT_FFT_COLS_F32 16
 #endif
 template <typename T, int L>
 constexpr int nl_col() {  // columns per tile for strided passes
