@@ -16,6 +16,8 @@ Modules
   projector  the composition image -> radially sampled derivative-Radon space
   recon      direct reconstruction from derivative-Radon data: the 3D ramp
              and the NUFFT transpose with angular quadrature (Section 2.3)
+  umbrella   resampling of the derivative-Radon space from the radial pattern
+             onto the cone-beam umbrella planes, method 2 (eq 2.15)
   complexity the paper's multiplication-count model (Section 2.4, eq 2.16-2.27)
 
 Conventions (where the paper is silent these are readings, not quotations):
@@ -32,4 +34,4 @@ Parity status of each function is stated in its docstring; every function is
 pinned by the tests in tests/test_oracle_*.py.
 """
 
-from . import nudft, kernels, nufft, radial, projector, recon, complexity  # noqa: F401
+from . import nudft, kernels, nufft, radial, projector, recon, umbrella, complexity  # noqa: F401
