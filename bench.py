@@ -327,12 +327,59 @@ def bench_recon(args):
     }), flush=True)
 
 
+def bench_umbrella(args):
+    """Radial -> umbrella resampling (method 2, eq 2.15) at the 128^3 set-up of
+    the cone-beam experiment: the c2 projector output (180 x 90 lines x 256)
+    resampled onto 256 projections x 256 x 256 detector lines; Msamples/s =
+    umbrella samples / time of one resampling, for J = 3 (the paper's) and 6."""
+    import numpy as np
+    import torch
+
+    import paper_1605_05231_amd as pkg
+    import synthetic
+
+    W = synthetic.WORKLOADS["c2"]
+    N, K, J, n_r = W.N, W.K, W.J, W.n_r
+    phi = synthetic.azimuths(W.n_phi)
+    th = synthetic.polar_angles(W.n_theta)
+    plan = pkg.Plan(N, K, J, dirs=W.directions(), n_r=n_r, dtype=torch.complex64)
+    d = plan.forward(torch.from_numpy(W.volume().astype(np.complex64)).cuda()).reshape(-1)
+    torch.cuda.synchronize()
+    n_proj = n_alpha = n_t = 2 * N
+    P = n_proj * n_alpha * n_t
+    res = {}
+    for Ju in (3, 6):
+        u = pkg.Umbrella(N, n_proj, n_alpha, n_t, W.n_phi, W.n_theta, n_r, th[0], th[1] - th[0], J=Ju)
+        out = torch.empty((n_proj, n_alpha, n_t), dtype=torch.complex64, device="cuda")
+        for _ in range(args.warmup):
+            u.resample(d, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            u.resample(d, out=out)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        res[Ju] = ms
+        log(f"[bench] umbrella J={Ju}: {ms:.3f} ms -> {P / (ms * 1e-3) / 1e6:.1f} Msamples/s")
+        u.close()
+    print(json.dumps({
+        "metric": "radial-to-umbrella resampling (method 2) Msamples/s at 128³",
+        "value": round(P / (res[6] * 1e-3) / 1e6, 2), "unit": "Msamples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(res[6], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "c2 derivative-Radon values (180 x 90 lines x 256) -> 256 projections "
+                               "x 256 x 256 umbrella planes, J = 6", "samples": P},
+        "J3_ms": round(res[3], 4),
+    }), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c5", "e1"],
+    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c5", "e1", "umbrella"],
                     help="c5: batch of 64 uneven volumes, replayed from HIP graphs; e1: direct "
                          "reconstruction at c3 and the angular-sampling experiment (own JSON lines)")
     ap.add_argument("--kernel", default="kb", choices=["kb", "minmax"])
@@ -375,6 +422,9 @@ def main():
         return
     if args.workload == "e1":
         bench_recon(args)
+        return
+    if args.workload == "umbrella":
+        bench_umbrella(args)
         return
     W = synthetic.WORKLOADS[args.workload]
     N, K, J, n_r = W.N, W.K, W.J, W.n_r

@@ -60,6 +60,7 @@ extern "C" {
 
 typedef struct nufftct_plan nufftct_plan;
 typedef struct nufftct_batch nufftct_batch;
+typedef struct nufftct_umbrella nufftct_umbrella;
 
 /* status codes */
 #define NUFFTCT_OK 0
@@ -215,6 +216,44 @@ int nufftct_plan_info(const nufftct_plan* plan, int64_t* N, int64_t* K, int* J,
  */
 int nufftct_set_timing(nufftct_plan* plan, int enable);
 int nufftct_get_stage_times(nufftct_plan* plan, double* ms, int64_t* count, int n);
+
+/*
+ * Radial -> umbrella resampling of the derivative-Radon space, method 2 of
+ * Section 2.1.3 (eq 2.15 with T_sparse2 the identity): step 2 of the
+ * forward projector (Section 2), from the radial pattern (eq 2.1) that the
+ * projector produces to the planes through the source positions of a
+ * circular cone-beam scan (the umbrella pattern, Figure 2.2).
+ *
+ * Geometry (voxel units): source circle of radius source_radius in the
+ * z = 0 plane, lambda_k = 2 pi k / n_proj; flat detector at source_detector
+ * from the source, perpendicular to the central ray, side detector_side,
+ * axes u = (-sin lambda, cos lambda, 0), v = (0, 0, 1).  Sample (k, i, j)
+ * is the plane through the source and the detector line
+ * u cos(alpha_i) + v sin(alpha_i) = t_j, alpha_i = pi i / n_alpha,
+ * t_j = (j - n_t/2) detector_side / n_t: normal nhat = normalised
+ * (e x q), e the line's direction, q from the source to the line's foot;
+ * rho = nhat . source.  Its (theta, phi) = (acos nhat_z, atan2 mod 2 pi).
+ *
+ * Interpolation: the radial grid phi_a = 2 pi a / n_phi, theta_b = theta0 +
+ * b dtheta, rho_j = j - n_r/2 is uniform in index space; per axis the J taps
+ * k0+1..k0+J, k0 = floor(t - J/2), weights sinc(u) psi(u) normalised over
+ * the taps (psi the Kaiser-Bessel window of width J, beta = 4J/3).  phi
+ * wraps; theta and rho taps off the grid contribute nothing.
+ *
+ * radial (device): n_phi * n_theta * n_r complex, layout [phi][theta][rho]
+ * (the projector's output for the (phi, theta) line grid).  out (device):
+ * n_proj * n_alpha * n_t complex, layout [k][i][j].  Complex64 for FP32,
+ * complex128 for FP64.  Create is host-only (no device memory).  Errors:
+ * EINVAL (counts < 1, products >= 2^31, non-positive or non-finite
+ * distances, J outside [2, 8], NULL or aliasing buffers), EUNSUPPORTED (weight
+ * fit), EHIP (launch).
+ */
+int nufftct_umbrella_create(nufftct_umbrella** out, int64_t n_proj, int64_t n_alpha, int64_t n_t,
+                            double source_radius, double source_detector, double detector_side,
+                            int64_t n_phi, int64_t n_theta, double theta0, double dtheta,
+                            int64_t n_r, int J, int precision, void* stream);
+int nufftct_umbrella_resample(nufftct_umbrella* u, const void* radial, void* out, void* stream);
+int nufftct_umbrella_destroy(nufftct_umbrella* u);
 
 /*
  * Batch of independent volumes of uneven size (each with its own radial

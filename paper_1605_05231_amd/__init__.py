@@ -17,8 +17,8 @@ from ._lib import (DERIV, DERIV_RADIAL, FP32, FP64, KERNEL_KB, KERNEL_MINMAX_KB,
                    STAGE_IFFT_CROP, STAGE_INTERP, STAGE_NAMES, STAGE_PAD_FFT, STAGE_RADIAL,
                    STAGE_RADIAL_ADJ, STAGE_SPREAD, NufftError)
 
-__all__ = ["Plan", "Batch", "NufftProjector", "project", "autotune", "radial_quadrature", "NufftError",
-           "version"]
+__all__ = ["Plan", "Batch", "Umbrella", "NufftProjector", "project", "autotune", "radial_quadrature",
+           "NufftError", "version"]
 
 
 def _torch():
@@ -226,6 +226,54 @@ def radial_quadrature(phi, theta) -> np.ndarray:
                                                      theta.ctypes.data_as(dp), len(theta),
                                                      w.ctypes.data_as(dp)))
     return w
+
+
+# Scan geometry of the circular cone-beam set-up (Section 3.2.1) in millimetres:
+# source-object and source-detector distances, detector side, object side.
+SCAN_MM = (1100.0, 1500.0, 512.0, 360.0)
+
+
+class Umbrella:
+    """Radial -> umbrella resampling (method 2, eq 2.15) for a circular
+    cone-beam scan; distances in voxels (default: the Section 3.2.1 set-up
+    scaled to an N^3 volume spanning the object)."""
+
+    def __init__(self, N, n_proj, n_alpha, n_t, n_phi, n_theta, n_r, theta0, dtheta, *, J=6,
+                 scan=None, dtype=None):
+        torch = _torch()
+        self.dtype = dtype or torch.complex64
+        prec = {torch.complex64: FP32, torch.complex128: FP64}[self.dtype]
+        if scan is None:
+            so, sd, det, obj = SCAN_MM
+            scan = (N * so / obj, N * sd / obj, N * det / obj)
+        self.n_in = int(n_phi) * int(n_theta) * int(n_r)
+        self.shape = (int(n_proj), int(n_alpha), int(n_t))
+        self._ptr = C.c_void_p()
+        _lib.check(_lib.load().nufftct_umbrella_create(
+            C.byref(self._ptr), int(n_proj), int(n_alpha), int(n_t), float(scan[0]), float(scan[1]),
+            float(scan[2]), int(n_phi), int(n_theta), float(theta0), float(dtheta), int(n_r), int(J),
+            prec, C.c_void_p(_stream_handle())))
+
+    def resample(self, d, out=None, *, stream=None):
+        torch = _torch()
+        _check_tensor(d, self.n_in, self.dtype, "d")
+        if out is None:
+            out = torch.empty(self.shape, dtype=self.dtype, device=d.device)
+        _check_tensor(out, self.shape[0] * self.shape[1] * self.shape[2], self.dtype, "out")
+        _lib.check(_lib.load().nufftct_umbrella_resample(self._ptr, d.data_ptr(), out.data_ptr(),
+                                                         C.c_void_p(_stream_handle(stream))))
+        return out
+
+    def close(self):
+        if getattr(self, "_ptr", None) is not None and self._ptr.value:
+            _lib.load().nufftct_umbrella_destroy(self._ptr)
+            self._ptr = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Batch:

@@ -34,6 +34,11 @@ SIGNATURES = {
     "nufftct_radial_quadrature": (C.c_int, [_dp, _i64, _dp, _i64, _dp]),
     "nufftct_set_line_weights": (C.c_int, [_p, _dp, _p]),
     "nufftct_reconstruct": (C.c_int, [_p, _p, _p, _p]),
+    "nufftct_umbrella_create": (C.c_int, [C.POINTER(_p), _i64, _i64, _i64, C.c_double, C.c_double,
+                                          C.c_double, _i64, _i64, C.c_double, C.c_double, _i64,
+                                          C.c_int, C.c_int, _p]),
+    "nufftct_umbrella_resample": (C.c_int, [_p, _p, _p, _p]),
+    "nufftct_umbrella_destroy": (C.c_int, [_p]),
     "nufftct_stage": (C.c_int, [_p, C.c_int, _p, _p, C.c_int, _p]),
     "nufftct_plan_destroy": (C.c_int, [_p]),
     "nufftct_plan_info": (C.c_int, [_p, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(C.c_int),

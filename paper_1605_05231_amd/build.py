@@ -15,8 +15,8 @@ BUILD = os.path.join(ROOT, "_build")
 # extra compile definitions for kernel-variant sweeps, e.g. "-DNUFFTCT_INTERP_NT=512"
 EXTRA = os.environ.get("NUFFTCT_EXTRA_FLAGS", "").split()
 
-SOURCES = ["plan.cpp", "tables.cpp", "batch.cpp", "k_fft_f32.hip", "k_fft_f64.hip",
-           "k_grid_f32.hip", "k_grid_f64.hip"]
+SOURCES = ["plan.cpp", "tables.cpp", "batch.cpp", "umbrella.cpp", "k_fft_f32.hip", "k_fft_f64.hip",
+           "k_grid_f32.hip", "k_grid_f64.hip", "k_umbrella.hip"]
 
 ARCH = os.environ.get("NUFFTCT_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -24,7 +24,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include"), "-Wno-unused-command-line-argument"]
 HOST_ONLY = {"plan.cpp": ["-ffp-contract=off"], "tables.cpp": ["-ffp-contract=off"],
-             "batch.cpp": []}
+             "batch.cpp": [], "umbrella.cpp": []}
 
 
 def hipcc() -> str:

@@ -125,3 +125,23 @@ def test_reconstruction_entry_points_reject_bad_arguments():
                                          w.ctypes.data_as(dp)) == _lib.EINVAL
     assert lib.nufftct_set_line_weights(None, w.ctypes.data_as(dp), None) == _lib.EINVAL
     assert lib.nufftct_reconstruct(None, C.c_void_p(16), C.c_void_p(32), None) == _lib.EINVAL
+
+
+def test_umbrella_create_is_host_only_and_validates():
+    # creation only checks arguments and sets constants on the host (no device memory)
+    lib = _lib.load()
+    for J in range(2, 9):
+        for prec in (_lib.FP32, _lib.FP64):
+            u = C.c_void_p()
+            rc = lib.nufftct_umbrella_create(C.byref(u), 4, 8, 16, 50.0, 70.0, 24.0, 32, 16, 0.2,
+                                             0.05, 32, J, prec, None)
+            assert rc == _lib.OK, (J, prec, lib.nufftct_last_error())
+            assert lib.nufftct_umbrella_destroy(u) == _lib.OK
+    u = C.c_void_p()
+    bad = [(0, 8, 16, 50.0, 70.0, 24.0, 32, 16, 0.2, 0.05, 32, 6),
+           (4, 8, 16, -1.0, 70.0, 24.0, 32, 16, 0.2, 0.05, 32, 6),
+           (4, 8, 16, 50.0, 70.0, 24.0, 32, 16, 0.2, 0.0, 32, 6),
+           (4, 8, 16, 50.0, 70.0, 24.0, 32, 16, 0.2, 0.05, 32, 9)]
+    for args in bad:
+        assert lib.nufftct_umbrella_create(C.byref(u), *args, _lib.FP32, None) == _lib.EINVAL, args
+    assert lib.nufftct_umbrella_resample(None, C.c_void_p(16), C.c_void_p(32), None) == _lib.EINVAL
