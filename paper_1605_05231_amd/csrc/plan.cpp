@@ -188,6 +188,36 @@ static void build_bins(const nufftct_plan& p, const std::vector<double>& geom, B
       for (int cls = 0; cls < step; ++cls) {
         int left = 0;
         for (int r = cls; r < 32; r += step) left += cnt[r + 1] - cnt[r];
+        if (step == 2) {
+          // groups of 16 points (one LDS pass of 16-byte reads) take one
+          // point from each of the 16 fullest residues of the class, so the
+          // buckets drain evenly and late groups keep distinct residues
+          int rs[16], nr = 0, take[32], rem[32];
+          for (int r = cls; r < 32; r += step) {
+            rs[nr++] = r;
+            take[r] = cnt[r];
+            rem[r] = cnt[r + 1] - cnt[r];
+          }
+          while (left > 0) {
+            std::stable_sort(rs, rs + nr, [&](int x, int y) { return rem[x] > rem[y]; });
+            int g = 0;
+            for (int k = 0; k < nr && g < 16 && rem[rs[k]] > 0; ++k, ++g) {
+              pts[o++] = bucket[take[rs[k]]++];
+              --rem[rs[k]];
+              --left;
+            }
+            while (g < 16 && left > 0) {  // fewer than 16 residues left
+              int best = rs[0];
+              for (int k = 1; k < nr; ++k)
+                if (rem[rs[k]] > rem[best]) best = rs[k];
+              pts[o++] = bucket[take[best]++];
+              --rem[best];
+              --left;
+              ++g;
+            }
+          }
+          continue;
+        }
         for (int round = 0; left > 0; ++round)
           for (int r = cls; r < 32; r += step)
             if (cnt[r] + round < cnt[r + 1]) {
