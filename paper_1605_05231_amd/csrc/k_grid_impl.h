@@ -584,6 +584,9 @@ __global__ __launch_bounds__(NT_SPREAD) void k_spread_bound(float* __restrict__ 
 // ranges are read once per workgroup into LDS, then every cell issues its
 // (mostly single) partial loads independently.  With the block layout of the
 // partials, the cells of a row read consecutive words of each block.
+#ifndef NUFFTCT_MERGE_PAIRS
+#define NUFFTCT_MERGE_PAIRS 1
+#endif
 #ifndef NUFFTCT_MERGE_MASKED
 #define NUFFTCT_MERGE_MASKED 1
 #endif
@@ -660,6 +663,95 @@ __global__ __launch_bounds__(TILE * TILE * TILE < NUFFTCT_MERGE_NT ? TILE * TILE
         for (int t = rng[2 * delta] + 1; t < rng[2 * delta + 1]; ++t)
           acc = cadd(acc, partials[t * PS + off[delta]]);
     grid[((int64_t)(t0 * TILE + i0) * K + (t1 * TILE + i1)) * K + (t2 * TILE + i2)] = acc;
+  }
+}
+
+// FP32 merge with two adjacent cells (i2 even, i2 + 1) per thread: the blocks
+// whose rows are TILE long are read and the grid written as 16-byte pairs
+// (part_base offsets and the per-task stride are even), the short-row blocks
+// one value at a time; the per-cell summation order is the one of k_merge.
+template <int TILE>
+__global__ __launch_bounds__(1024) void k_merge_pairs(const cx<float>* __restrict__ partials,
+                                                      const int32_t* __restrict__ bin_tasks,
+                                                      cx<float>* __restrict__ grid, int nb, int K,
+                                                      int R, double r2) {
+  constexpr int TT2 = TILE * TILE * TILE / 2;
+  constexpr int NTM = TT2 < 1024 ? TT2 : 1024;
+  constexpr int PER = TT2 / NTM;
+  const int64_t PS = part_stride(TILE, R);
+  const int tile = (int)blockIdx.x;
+  const int t2 = tile % nb, t1 = (tile / nb) % nb, t0 = tile / (nb * nb);
+  {
+    double d2 = 0.0;
+    const int ts[3] = {t0, t1, t2};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int lo = ts[d] * TILE - K / 2, hi = lo + TILE - 1;
+      const double c = lo > 0 ? (double)lo : (hi < 0 ? (double)(-hi) : 0.0);
+      d2 += c * c;
+    }
+    if (d2 > r2) return;
+  }
+  __shared__ int rng[16];
+  if (threadIdx.x < 8) {
+    const int delta = threadIdx.x;
+    const int d0 = (delta >> 2) & 1, d1 = (delta >> 1) & 1, d2 = delta & 1;
+    const int sb = (((t0 - d0 + nb) % nb) * nb + (t1 - d1 + nb) % nb) * nb + (t2 - d2 + nb) % nb;
+    rng[2 * delta] = bin_tasks[sb];
+    rng[2 * delta + 1] = bin_tasks[sb + 1];
+  }
+  __syncthreads();
+  const float4* p4 = reinterpret_cast<const float4*>(partials);
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int idx = (int)threadIdx.x + k * NTM;
+    const int i2 = 2 * (idx % (TILE / 2)), i1 = (idx / (TILE / 2)) % TILE, i0 = idx / (TILE * TILE / 2);
+    cx<float> a0 = {0, 0}, a1 = {0, 0};
+    int64_t off[8];
+    bool h0[8], h1[8];
+#pragma unroll
+    for (int delta = 0; delta < 8; ++delta) {
+      const int d0 = (delta >> 2) & 1, d1 = (delta >> 1) & 1, d2 = delta & 1;
+      const int e0 = part_ext(d0, TILE, R), e1 = part_ext(d1, TILE, R), e2 = part_ext(d2, TILE, R);
+      const bool any = i0 < e0 && i1 < e1 && rng[2 * delta] < rng[2 * delta + 1];
+      h0[delta] = any && i2 < e2;
+      h1[delta] = any && i2 + 1 < e2;
+      off[delta] = part_base(delta, TILE, R) + (i0 * e1 + i1) * e2 + i2;
+    }
+    cx<float> f0[8], f1[8];
+#pragma unroll
+    for (int delta = 0; delta < 8; ++delta) {
+      f0[delta] = cx<float>{0, 0};
+      f1[delta] = cx<float>{0, 0};
+      const int64_t o = rng[2 * delta] * PS + off[delta];
+      if ((delta & 1) == 0) {  // rows of TILE cells: one 16-byte read for both cells
+        if (h0[delta]) {
+          const float4 v = p4[o >> 1];
+          f0[delta] = cx<float>{v.x, v.y};
+          f1[delta] = cx<float>{v.z, v.w};
+        }
+      } else {
+        if (h0[delta]) f0[delta] = partials[o];
+        if (h1[delta]) f1[delta] = partials[o + 1];
+      }
+    }
+#pragma unroll
+    for (int delta = 0; delta < 8; ++delta) {
+      if (h0[delta]) a0 = cadd(a0, f0[delta]);
+      if (h1[delta]) a1 = cadd(a1, f1[delta]);
+    }
+#pragma unroll
+    for (int delta = 0; delta < 8; ++delta) {
+      if (h0[delta])
+        for (int t = rng[2 * delta] + 1; t < rng[2 * delta + 1]; ++t)
+          a0 = cadd(a0, partials[t * PS + off[delta]]);
+      if (h1[delta])
+        for (int t = rng[2 * delta] + 1; t < rng[2 * delta + 1]; ++t)
+          a1 = cadd(a1, partials[t * PS + off[delta] + 1]);
+    }
+    float4* g4 = reinterpret_cast<float4*>(
+        grid + ((int64_t)(t0 * TILE + i0) * K + (t1 * TILE + i1)) * K + (t2 * TILE + i2));
+    *g4 = make_float4(a0.x, a0.y, a1.x, a1.y);
   }
 }
 
@@ -744,6 +836,13 @@ hipError_t merge(const nufftct_plan& p, void* grid, hipStream_t st, bool prune) 
   const int R = p.J - 1;
   const double r2 = prune ? p.ball_r2 : 1e300;
   const dim3 grd((unsigned)((int64_t)p.nb * p.nb * p.nb));
+#if NUFFTCT_MERGE_PAIRS
+  if (p.tile == 16 && sizeof(T) == 4) {
+    hipLaunchKernelGGL((k_merge_pairs<16>), grd, dim3(1024), 0, st, (const cx<float>*)p.d_partials,
+                       p.d_bin_tasks, (cx<float>*)grid, p.nb, (int)p.K, R, r2);
+    return hipGetLastError();
+  }
+#endif
   if (p.tile == 16)
     hipLaunchKernelGGL((k_merge<T, 16>), grd, dim3(4096 < NUFFTCT_MERGE_NT ? 4096 : NUFFTCT_MERGE_NT), 0, st, (const cx<T>*)p.d_partials,
                        p.d_bin_tasks, (cx<T>*)grid, p.nb, (int)p.K, R, r2);
