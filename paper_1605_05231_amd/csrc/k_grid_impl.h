@@ -587,6 +587,9 @@ __global__ __launch_bounds__(NT_SPREAD) void k_spread_bound(float* __restrict__ 
 #ifndef NUFFTCT_MERGE_PAIRS
 #define NUFFTCT_MERGE_PAIRS 1
 #endif
+#ifndef NUFFTCT_MERGE_CELLS
+#define NUFFTCT_MERGE_CELLS 2
+#endif
 #ifndef NUFFTCT_MERGE_MASKED
 #define NUFFTCT_MERGE_MASKED 1
 #endif
@@ -666,18 +669,19 @@ __global__ __launch_bounds__(TILE * TILE * TILE < NUFFTCT_MERGE_NT ? TILE * TILE
   }
 }
 
-// FP32 merge with two adjacent cells (i2 even, i2 + 1) per thread: the blocks
-// whose rows are TILE long are read and the grid written as 16-byte pairs
-// (part_base offsets and the per-task stride are even), the short-row blocks
-// one value at a time; the per-cell summation order is the one of k_merge.
-template <int TILE>
+// FP32 merge with C adjacent cells (C = 2 or 4; i2 a multiple of C) per
+// thread: the blocks whose rows are TILE long are read and the grid written
+// in 16-byte pairs (part_base offsets and the per-task stride are even), the
+// short-row blocks one value at a time; the per-cell summation order is the
+// one of k_merge.
+template <int TILE, int C>
 __global__ __launch_bounds__(1024) void k_merge_pairs(const cx<float>* __restrict__ partials,
                                                       const int32_t* __restrict__ bin_tasks,
                                                       cx<float>* __restrict__ grid, int nb, int K,
                                                       int R, double r2) {
-  constexpr int TT2 = TILE * TILE * TILE / 2;
-  constexpr int NTM = TT2 < 1024 ? TT2 : 1024;
-  constexpr int PER = TT2 / NTM;
+  constexpr int TTC = TILE * TILE * TILE / C;
+  constexpr int NTM = TTC < 1024 ? TTC : 1024;
+  constexpr int PER = TTC / NTM;
   const int64_t PS = part_stride(TILE, R);
   const int tile = (int)blockIdx.x;
   const int t2 = tile % nb, t1 = (tile / nb) % nb, t0 = tile / (nb * nb);
@@ -705,53 +709,59 @@ __global__ __launch_bounds__(1024) void k_merge_pairs(const cx<float>* __restric
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
     const int idx = (int)threadIdx.x + k * NTM;
-    const int i2 = 2 * (idx % (TILE / 2)), i1 = (idx / (TILE / 2)) % TILE, i0 = idx / (TILE * TILE / 2);
-    cx<float> a0 = {0, 0}, a1 = {0, 0};
+    const int i2 = C * (idx % (TILE / C)), i1 = (idx / (TILE / C)) % TILE;
+    const int i0 = idx / (TILE * TILE / C);
+    cx<float> acc[C];
+#pragma unroll
+    for (int q = 0; q < C; ++q) acc[q] = cx<float>{0, 0};
     int64_t off[8];
-    bool h0[8], h1[8];
+    bool any[8];
+    int e2s[8];
 #pragma unroll
     for (int delta = 0; delta < 8; ++delta) {
       const int d0 = (delta >> 2) & 1, d1 = (delta >> 1) & 1, d2 = delta & 1;
       const int e0 = part_ext(d0, TILE, R), e1 = part_ext(d1, TILE, R), e2 = part_ext(d2, TILE, R);
-      const bool any = i0 < e0 && i1 < e1 && rng[2 * delta] < rng[2 * delta + 1];
-      h0[delta] = any && i2 < e2;
-      h1[delta] = any && i2 + 1 < e2;
+      any[delta] = i0 < e0 && i1 < e1 && i2 < e2 && rng[2 * delta] < rng[2 * delta + 1];
+      e2s[delta] = e2;
       off[delta] = part_base(delta, TILE, R) + (i0 * e1 + i1) * e2 + i2;
     }
-    cx<float> f0[8], f1[8];
+    cx<float> f[8][C];
 #pragma unroll
     for (int delta = 0; delta < 8; ++delta) {
-      f0[delta] = cx<float>{0, 0};
-      f1[delta] = cx<float>{0, 0};
+#pragma unroll
+      for (int q = 0; q < C; ++q) f[delta][q] = cx<float>{0, 0};
       const int64_t o = rng[2 * delta] * PS + off[delta];
-      if ((delta & 1) == 0) {  // rows of TILE cells: one 16-byte read for both cells
-        if (h0[delta]) {
-          const float4 v = p4[o >> 1];
-          f0[delta] = cx<float>{v.x, v.y};
-          f1[delta] = cx<float>{v.z, v.w};
+      if ((delta & 1) == 0) {  // rows of TILE cells: 16-byte reads of cell pairs
+        if (any[delta]) {
+#pragma unroll
+          for (int q = 0; q < C; q += 2) {
+            const float4 v = p4[(o + q) >> 1];
+            f[delta][q] = cx<float>{v.x, v.y};
+            f[delta][q + 1] = cx<float>{v.z, v.w};
+          }
         }
       } else {
-        if (h0[delta]) f0[delta] = partials[o];
-        if (h1[delta]) f1[delta] = partials[o + 1];
+#pragma unroll
+        for (int q = 0; q < C; ++q)
+          if (any[delta] && i2 + q < e2s[delta]) f[delta][q] = partials[o + q];
       }
     }
 #pragma unroll
-    for (int delta = 0; delta < 8; ++delta) {
-      if (h0[delta]) a0 = cadd(a0, f0[delta]);
-      if (h1[delta]) a1 = cadd(a1, f1[delta]);
-    }
+    for (int delta = 0; delta < 8; ++delta)
 #pragma unroll
-    for (int delta = 0; delta < 8; ++delta) {
-      if (h0[delta])
-        for (int t = rng[2 * delta] + 1; t < rng[2 * delta + 1]; ++t)
-          a0 = cadd(a0, partials[t * PS + off[delta]]);
-      if (h1[delta])
-        for (int t = rng[2 * delta] + 1; t < rng[2 * delta + 1]; ++t)
-          a1 = cadd(a1, partials[t * PS + off[delta] + 1]);
-    }
+      for (int q = 0; q < C; ++q)
+        if (any[delta] && i2 + q < e2s[delta]) acc[q] = cadd(acc[q], f[delta][q]);
+#pragma unroll
+    for (int delta = 0; delta < 8; ++delta)
+#pragma unroll
+      for (int q = 0; q < C; ++q)
+        if (any[delta] && i2 + q < e2s[delta])
+          for (int t = rng[2 * delta] + 1; t < rng[2 * delta + 1]; ++t)
+            acc[q] = cadd(acc[q], partials[t * PS + off[delta] + q]);
     float4* g4 = reinterpret_cast<float4*>(
         grid + ((int64_t)(t0 * TILE + i0) * K + (t1 * TILE + i1)) * K + (t2 * TILE + i2));
-    *g4 = make_float4(a0.x, a0.y, a1.x, a1.y);
+#pragma unroll
+    for (int q = 0; q < C; q += 2) g4[q >> 1] = make_float4(acc[q].x, acc[q].y, acc[q + 1].x, acc[q + 1].y);
   }
 }
 
@@ -838,7 +848,8 @@ hipError_t merge(const nufftct_plan& p, void* grid, hipStream_t st, bool prune) 
   const dim3 grd((unsigned)((int64_t)p.nb * p.nb * p.nb));
 #if NUFFTCT_MERGE_PAIRS
   if (p.tile == 16 && sizeof(T) == 4) {
-    hipLaunchKernelGGL((k_merge_pairs<16>), grd, dim3(1024), 0, st, (const cx<float>*)p.d_partials,
+    hipLaunchKernelGGL((k_merge_pairs<16, NUFFTCT_MERGE_CELLS>), grd, dim3(1024), 0, st,
+                       (const cx<float>*)p.d_partials,
                        p.d_bin_tasks, (cx<float>*)grid, p.nb, (int)p.K, R, r2);
     return hipGetLastError();
   }
