@@ -124,7 +124,7 @@ int nufftct_plan_create_radial(nufftct_plan** out, int64_t N, int64_t K, int J, 
 
 /*
  * Autotune the tiling of radial plans with these parameters: builds candidate
- * plans (tile edge 16 or 8 cells x 1024..8192 points per task), times one
+ * plans (tile edge 16 or 8 cells x 1024..16384 points per task), times one
  * forward + adjoint (flags as for nufftct_forward) of each on `stream`, and
  * records the fastest in a process-wide table that every later plan creation
  * with the same (N, K, J, kernel, precision, n_lines, n_r) uses.  With the

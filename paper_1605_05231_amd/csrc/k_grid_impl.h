@@ -600,12 +600,12 @@ template <typename T, int TILE>
 __global__ __launch_bounds__(TILE * TILE * TILE < NUFFTCT_MERGE_NT ? TILE * TILE * TILE
                                                                     : NUFFTCT_MERGE_NT) void k_merge(
     const cx<T>* __restrict__ partials, const int32_t* __restrict__ bin_tasks,
-    cx<T>* __restrict__ grid, int nb, int K, int R, double r2) {
+    const int32_t* __restrict__ order, cx<T>* __restrict__ grid, int nb, int K, int R, double r2) {
   constexpr int TT = TILE * TILE * TILE;
   constexpr int NTM = TT < NUFFTCT_MERGE_NT ? TT : NUFFTCT_MERGE_NT;
   constexpr int PER = TT / NTM;
   const int64_t PS = part_stride(TILE, R);
-  const int tile = (int)blockIdx.x;
+  const int tile = order[blockIdx.x];
   const int t2 = tile % nb, t1 = (tile / nb) % nb, t0 = tile / (nb * nb);
   {
     // tiles wholly outside the ball holding every tap are never read
@@ -677,13 +677,14 @@ __global__ __launch_bounds__(TILE * TILE * TILE < NUFFTCT_MERGE_NT ? TILE * TILE
 template <int TILE, int C>
 __global__ __launch_bounds__(1024) void k_merge_pairs(const cx<float>* __restrict__ partials,
                                                       const int32_t* __restrict__ bin_tasks,
+                                                      const int32_t* __restrict__ order,
                                                       cx<float>* __restrict__ grid, int nb, int K,
                                                       int R, double r2) {
   constexpr int TTC = TILE * TILE * TILE / C;
   constexpr int NTM = TTC < 1024 ? TTC : 1024;
   constexpr int PER = TTC / NTM;
   const int64_t PS = part_stride(TILE, R);
-  const int tile = (int)blockIdx.x;
+  const int tile = order[blockIdx.x];
   const int t2 = tile % nb, t1 = (tile / nb) % nb, t0 = tile / (nb * nb);
   {
     double d2 = 0.0;
@@ -850,16 +851,16 @@ hipError_t merge(const nufftct_plan& p, void* grid, hipStream_t st, bool prune) 
   if (p.tile == 16 && sizeof(T) == 4) {
     hipLaunchKernelGGL((k_merge_pairs<16, NUFFTCT_MERGE_CELLS>), grd, dim3(1024), 0, st,
                        (const cx<float>*)p.d_partials,
-                       p.d_bin_tasks, (cx<float>*)grid, p.nb, (int)p.K, R, r2);
+                       p.d_bin_tasks, p.d_merge_order, (cx<float>*)grid, p.nb, (int)p.K, R, r2);
     return hipGetLastError();
   }
 #endif
   if (p.tile == 16)
     hipLaunchKernelGGL((k_merge<T, 16>), grd, dim3(4096 < NUFFTCT_MERGE_NT ? 4096 : NUFFTCT_MERGE_NT), 0, st, (const cx<T>*)p.d_partials,
-                       p.d_bin_tasks, (cx<T>*)grid, p.nb, (int)p.K, R, r2);
+                       p.d_bin_tasks, p.d_merge_order, (cx<T>*)grid, p.nb, (int)p.K, R, r2);
   else if (p.tile == 8)
     hipLaunchKernelGGL((k_merge<T, 8>), grd, dim3(512 < NUFFTCT_MERGE_NT ? 512 : NUFFTCT_MERGE_NT), 0, st, (const cx<T>*)p.d_partials,
-                       p.d_bin_tasks, (cx<T>*)grid, p.nb, (int)p.K, R, r2);
+                       p.d_bin_tasks, p.d_merge_order, (cx<T>*)grid, p.nb, (int)p.K, R, r2);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

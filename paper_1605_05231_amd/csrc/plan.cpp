@@ -249,6 +249,7 @@ static void free_plan(nufftct_plan* p) {
   hipFree(p->d_perm_s);
   hipFree(p->d_tasks);
   hipFree(p->d_bin_tasks);
+  hipFree(p->d_merge_order);
   hipFree(p->d_partials);
   hipFree(p->d_bound);
   hipFree(p->d_line_w);
@@ -524,6 +525,28 @@ static int create(nufftct_plan** out, int64_t N, int64_t K, int J, int kernel, d
     if ((rc = upload((void**)&p->d_tasks, B.tasks.data(), B.tasks.size(), st))) return bail(rc);
     if ((rc = upload((void**)&p->d_bin_tasks, B.bin_tasks.data(), B.bin_tasks.size(), st)))
       return bail(rc);
+    {
+      // merge dispatch order: the tiles that sum the most partial cells first,
+      // so that the dense centre's long per-cell task loops do not form the tail
+      const int nb = p->nb, T = p->tile, R = J - 1;
+      const int64_t nt = (int64_t)nb * nb * nb;
+      std::vector<int64_t> cost(nt, 0);
+      for (int64_t t = 0; t < nt; ++t) {
+        const int t2 = (int)(t % nb), t1 = (int)((t / nb) % nb), t0 = (int)(t / ((int64_t)nb * nb));
+        for (int delta = 0; delta < 8; ++delta) {
+          const int d0 = (delta >> 2) & 1, d1 = (delta >> 1) & 1, d2 = delta & 1;
+          const int64_t sb = (((int64_t)((t0 - d0 + nb) % nb) * nb + (t1 - d1 + nb) % nb) * nb) +
+                             (t2 - d2 + nb) % nb;
+          const int64_t cells = (int64_t)(d0 ? R : T) * (d1 ? R : T) * (d2 ? R : T);
+          cost[t] += (int64_t)(B.bin_tasks[sb + 1] - B.bin_tasks[sb]) * cells;
+        }
+      }
+      std::vector<int32_t> order(nt);
+      for (int64_t t = 0; t < nt; ++t) order[t] = (int32_t)t;
+      std::stable_sort(order.begin(), order.end(),
+                       [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+      if ((rc = upload((void**)&p->d_merge_order, order.data(), order.size(), st))) return bail(rc);
+    }
     const size_t cxb = precision == NUFFTCT_FP32 ? 8 : 16;
     // per-task stride: the halo's S^3 cells rounded up to 16 (the merge's
     // loads then start on 128-byte lines)
@@ -751,7 +774,7 @@ int nufftct_autotune_radial(int64_t N, int64_t K, int J, int kernel, double beta
   hipEventCreate(&e0);
   hipEventCreate(&e1);
   const int tiles[2] = {16, 8};
-  const int mps[4] = {1024, 2048, 4096, 8192};
+  const int mps[6] = {1024, 2048, 4096, 8192, 12288, 16384};
   double best = 1e30;
   TuneVal bv{0, 0};
   for (int t : tiles)
