@@ -397,6 +397,7 @@ __attribute__((amdgpu_waves_per_eu(NUFFTCT_SPREAD_WAVES_PER_EU))) void k_spread(
                                                       cx<T>* __restrict__ partials,
                                                       const int32_t* __restrict__ perm,
                                                       const TileTask* __restrict__ tasks,
+                                                      const int32_t* __restrict__ torder,
                                                       const float* __restrict__ bound,
                                                       XcdSplit xs, PointGeom g, int nb,
                                                       WeightPoly<T, DEG> P) {
@@ -409,8 +410,9 @@ __attribute__((amdgpu_waves_per_eu(NUFFTCT_SPREAD_WAVES_PER_EU))) void k_spread(
   __shared__ double acc[FIXED ? SS : 2 * SS];
   __shared__ unsigned int s_maxbits;
   unsigned long long* accp = reinterpret_cast<unsigned long long*>(acc);
-  const int64_t task_id = xcd_task(blockIdx.x, xs);
+  int64_t task_id = xcd_task(blockIdx.x, xs);
   if (task_id < 0) return;
+  if (torder) task_id = torder[task_id];  // largest tasks of each XCD range first
   const TileTask tk = tasks[task_id];
   const int b2 = tk.bin % nb, b1 = (tk.bin / nb) % nb, b0 = tk.bin / (nb * nb);
   const int o0 = b0 * TILE, o1 = b1 * TILE, o2 = b2 * TILE;
@@ -799,7 +801,7 @@ hipError_t launch_one(const nufftct_plan& p, const void* src, void* dst, hipStre
     if constexpr (OP == OP_SPREAD) {
       hipLaunchKernelGGL((k_spread<T, J, TILE, CW, DEG>), grd, dim3(NT_SPREAD), 0, st,
                          (const cx<T>*)src, (cx<T>*)p.d_partials, p.d_perm_s, p.d_tasks,
-                         p.d_bound, p.xsplit, g, p.nb, P);
+                         p.d_spread_order, p.d_bound, p.xsplit, g, p.nb, P);
     } else if constexpr (OP == OP_BOUND) {
       hipLaunchKernelGGL((k_spread_bound<T, J, TILE, CW, DEG>), grd, dim3(NT_SPREAD), 0, st,
                          p.d_bound, p.d_perm_s, p.d_tasks, p.xsplit, g, p.nb, P);

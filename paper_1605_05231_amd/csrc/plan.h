@@ -70,6 +70,7 @@ struct nufftct_plan {
   XcdSplit xsplit{};               // per-XCD task ranges of equal point count
   int32_t* d_bin_tasks = nullptr;  // nb^3 + 1 offsets: tasks of bin b are [o[b], o[b+1])
   int32_t* d_merge_order = nullptr;  // nb^3 tiles in merge dispatch order, heaviest first
+  int32_t* d_spread_order = nullptr; // ntasks: spreading dispatch order (per XCD range, largest first)
   void* d_partials = nullptr;      // per task, its spread halo tile (S^3 complex)
   float* d_bound = nullptr;        // FP32: per task, max over halo cells of sum |w|
   double* d_line_w = nullptr;      // radial plans: per-line reconstruction weights (optional)
