@@ -24,6 +24,9 @@
 #include "fft_lds.h"
 #include "plan.h"
 
+#ifndef NUFFTCT_FFT_TW_LDS
+#define NUFFTCT_FFT_TW_LDS 1
+#endif
 #ifndef NUFFTCT_FFT_XCD_COLS
 #define NUFFTCT_FFT_XCD_COLS 1
 #endif
@@ -121,6 +124,15 @@ __global__ __launch_bounds__(NTS) void k_fft_strided(cx<T>* __restrict__ grid,
   constexpr int NL = nl_col<T, L>();
   constexpr int K = L;
   __shared__ cx<T> buf[fft::tile_elems<false, L, NL>()];
+#if NUFFTCT_FFT_TW_LDS
+  // the twiddle table in LDS: every stage's twiddle reads become LDS reads
+  // (broadcast across the columns of a butterfly row)
+  __shared__ cx<T> twl[L];
+  for (int i = threadIdx.x; i < L; i += NTS) twl[i] = tw[i];
+  const cx<T>* twp = twl;
+#else
+  const cx<T>* twp = tw;
+#endif
   const int tid = threadIdx.x;
   const int h = N / 2;
   const int o = blockIdx.y;
@@ -168,7 +180,7 @@ __global__ __launch_bounds__(NTS) void k_fft_strided(cx<T>* __restrict__ grid,
     buf[idx] = v;  // column-major address e*NL + line
   }
   __syncthreads();
-  fft::run<T, L, NL, NTS, false, S>(buf, tw, tid);
+  fft::run<T, L, NL, NTS, false, S>(buf, twp, tid);
   for (int idx = tid; idx < NL * L; idx += NTS) {
     const int line = idx % NL, e = idx / NL;
     const int m = centred_of(e, K);
