@@ -70,6 +70,13 @@ __global__ __launch_bounds__(NT) void k_pad_fft_x(const cx<T>* __restrict__ vol,
   constexpr int NL = nl_line<T, L>();
   constexpr int K = L;
   __shared__ cx<T> buf[fft::tile_elems<true, L, NL>()];
+#if NUFFTCT_FFT_TW_LDS
+  __shared__ cx<T> twl[L];
+  for (int i = threadIdx.x; i < L; i += NT) twl[i] = tw[i];
+  const cx<T>* twp = twl;
+#else
+  const cx<T>* twp = tw;
+#endif
   const int tid = threadIdx.x;
   const int64_t nlines = (int64_t)N * N;
   const int64_t line0 = (int64_t)blockIdx.x * NL;
@@ -90,7 +97,7 @@ __global__ __launch_bounds__(NT) void k_pad_fft_x(const cx<T>* __restrict__ vol,
     buf[fft::addr<true, L, NL>(line, e)] = v;
   }
   __syncthreads();
-  fft::run<T, L, NL, NT, true, -1>(buf, tw, tid);
+  fft::run<T, L, NL, NT, true, -1>(buf, twp, tid);
   for (int idx = tid; idx < NL * L; idx += NT) {
     const int line = idx / L, e = idx % L;
     const int64_t gl = line0 + line;
@@ -203,6 +210,13 @@ __global__ __launch_bounds__(NT) void k_ifft_crop_x(const cx<T>* __restrict__ gr
   constexpr int NL = nl_line<T, L>();
   constexpr int K = L;
   __shared__ cx<T> buf[fft::tile_elems<true, L, NL>()];
+#if NUFFTCT_FFT_TW_LDS
+  __shared__ cx<T> twl[L];
+  for (int i = threadIdx.x; i < L; i += NT) twl[i] = tw[i];
+  const cx<T>* twp = twl;
+#else
+  const cx<T>* twp = tw;
+#endif
   const int tid = threadIdx.x;
   const int64_t nlines = (int64_t)N * N;
   const int64_t line0 = (int64_t)blockIdx.x * NL;
@@ -219,7 +233,7 @@ __global__ __launch_bounds__(NT) void k_ifft_crop_x(const cx<T>* __restrict__ gr
     buf[fft::addr<true, L, NL>(line, e)] = v;
   }
   __syncthreads();
-  fft::run<T, L, NL, NT, true, +1>(buf, tw, tid);
+  fft::run<T, L, NL, NT, true, +1>(buf, twp, tid);
   for (int idx = tid; idx < NL * N; idx += NT) {
     const int line = idx / N, n2 = idx % N;
     const int64_t gl = line0 + line;
@@ -251,6 +265,13 @@ __global__ __launch_bounds__(NT) void k_radial(const cx<T>* __restrict__ in,
                                                double w_scale) {
   constexpr int NL = nl_line<T, L>();
   __shared__ cx<T> buf[fft::tile_elems<true, L, NL>()];
+#if NUFFTCT_FFT_TW_LDS
+  __shared__ cx<T> twl[L];
+  for (int i = threadIdx.x; i < L; i += NT) twl[i] = tw[i];
+  const cx<T>* twp = twl;
+#else
+  const cx<T>* twp = tw;
+#endif
   const int tid = threadIdx.x;
   const int64_t line0 = (int64_t)blockIdx.x * NL;
   const T post = (T)(((L / 2) & 1 ? -1.0 : 1.0) / (double)L);
@@ -269,7 +290,7 @@ __global__ __launch_bounds__(NT) void k_radial(const cx<T>* __restrict__ in,
     buf[fft::addr<true, L, NL>(line, e)] = v;
   }
   __syncthreads();
-  fft::run<T, L, NL, NT, true, ADJ ? -1 : +1>(buf, tw, tid);
+  fft::run<T, L, NL, NT, true, ADJ ? -1 : +1>(buf, twp, tid);
   for (int idx = tid; idx < NL * L; idx += NT) {
     const int line = idx / L, e = idx % L;
     const int64_t gl = line0 + line;
