@@ -13,7 +13,8 @@
 #define NUFFTCT_SPREAD_NT NUFFTCT_SPREAD32_NT
 #define NUFFTCT_SPREAD_WAVES_PER_EU NUFFTCT_SPREAD32_WAVES
 // FP32 interpolation: two 512-thread workgroups per CU (LDS-bound) within
-// 128 VGPRs, which leaves no room for a one-ahead prefetch of the point data.
+// 128 VGPRs, which leaves room for a one-ahead prefetch of the next point's id
+// only (not of its geometry).
 #ifndef NUFFTCT_INTERP32_NT
 #define NUFFTCT_INTERP32_NT 512
 #endif
@@ -21,7 +22,7 @@
 #define NUFFTCT_INTERP32_WAVES 4
 #endif
 #ifndef NUFFTCT_INTERP32_PREFETCH
-#define NUFFTCT_INTERP32_PREFETCH 0
+#define NUFFTCT_INTERP32_PREFETCH 2
 #endif
 #define NUFFTCT_INTERP_NT NUFFTCT_INTERP32_NT
 #define NUFFTCT_INTERP_WAVES_PER_EU NUFFTCT_INTERP32_WAVES

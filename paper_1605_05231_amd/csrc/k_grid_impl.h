@@ -66,11 +66,10 @@ struct PtRaw {
   double r, a0, a1, a2;
 };
 
-__device__ __forceinline__ PtRaw fetch_point(const PointGeom& g, const int32_t* __restrict__ perm,
-                                             int idx) {
+__device__ __forceinline__ PtRaw point_of(const PointGeom& g, int pid) {
 #pragma clang fp contract(off)
   PtRaw q;
-  q.p = perm[idx];
+  q.p = pid;
   if (g.n_r) {
     // line and sample of the point: q.p / n_r through a double reciprocal,
     // corrected by one either way
@@ -94,6 +93,11 @@ __device__ __forceinline__ PtRaw fetch_point(const PointGeom& g, const int32_t* 
     q.a2 = g.pts[3 * (int64_t)q.p + 2];
   }
   return q;
+}
+
+__device__ __forceinline__ PtRaw fetch_point(const PointGeom& g, const int32_t* __restrict__ perm,
+                                             int idx) {
+  return point_of(g, perm[idx]);
 }
 
 // First tap (centred, wrapped to [0, K)) and fractional offset per axis, with
@@ -326,14 +330,20 @@ __attribute__((amdgpu_waves_per_eu(NUFFTCT_INTERP_WAVES_PER_EU))) void k_interp(
     tile[(i0 * S + i1) * S2 + i2] = grid[((int64_t)c0 * K + c1) * K + c2];
   }
   __syncthreads();
-#if NUFFTCT_INTERP_PREFETCH
+#if NUFFTCT_INTERP_PREFETCH == 1
   PtRaw nxt;
   if ((int)threadIdx.x < tk.count) nxt = fetch_point(g, perm, tk.start + threadIdx.x);
+#elif NUFFTCT_INTERP_PREFETCH == 2
+  // only the next point id is fetched one iteration ahead (one register)
+  int pnxt = (int)threadIdx.x < tk.count ? perm[tk.start + threadIdx.x] : 0;
 #endif
   for (int i = threadIdx.x; i < tk.count; i += NT_INTERP) {
-#if NUFFTCT_INTERP_PREFETCH
+#if NUFFTCT_INTERP_PREFETCH == 1
     const PtRaw cur = nxt;
     if (i + NT_INTERP < tk.count) nxt = fetch_point(g, perm, tk.start + i + NT_INTERP);
+#elif NUFFTCT_INTERP_PREFETCH == 2
+    const PtRaw cur = point_of(g, pnxt);
+    if (i + NT_INTERP < tk.count) pnxt = perm[tk.start + i + NT_INTERP];
 #else
     const PtRaw cur = fetch_point(g, perm, tk.start + i);
 #endif
