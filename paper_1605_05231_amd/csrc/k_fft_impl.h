@@ -58,6 +58,34 @@ constexpr int nl_col() {  // columns per tile for strided passes
 }
 
 __device__ __forceinline__ int centred_of(int e, int K) { return e < K / 2 ? e : e - K; }
+
+// Staging of a tile of NE elements by NTH threads: thread t handles elements
+// t, t + NTH, ...  All of its loads are issued before any is written to LDS,
+// so that they are in flight together (a loop that writes each element as it
+// arrives keeps one load per thread in flight and leaves the pass bound by
+// memory latency rather than bandwidth).
+#ifndef NUFFTCT_FFT_BATCH_LOADS
+#define NUFFTCT_FFT_BATCH_LOADS 1
+#endif
+template <typename T, int NE, int NTH, typename Ld, typename St>
+__device__ __forceinline__ void stage_tile(int tid, Ld&& ld, St&& st) {
+#if NUFFTCT_FFT_BATCH_LOADS
+  constexpr int PER = (NE + NTH - 1) / NTH;
+  cx<T> v[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int idx = tid + k * NTH;
+    v[k] = (NE % NTH == 0 || idx < NE) ? ld(idx) : cx<T>{0, 0};
+  }
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int idx = tid + k * NTH;
+    if (NE % NTH == 0 || idx < NE) st(idx, v[k]);
+  }
+#else
+  for (int idx = tid; idx < NE; idx += NTH) st(idx, ld(idx));
+#endif
+}
 __device__ __forceinline__ int wrap_of(int m, int K) { return m >= 0 ? m : m + K; }
 
 // ---------------------------------------------------------------------------
@@ -81,21 +109,24 @@ __global__ __launch_bounds__(NT) void k_pad_fft_x(const cx<T>* __restrict__ vol,
   const int64_t nlines = (int64_t)N * N;
   const int64_t line0 = (int64_t)blockIdx.x * NL;
   const int h = N / 2;
-  for (int idx = tid; idx < NL * L; idx += NT) {
-    const int line = idx / L, e = idx % L;
-    const int64_t gl = line0 + line;
-    cx<T> v = {0, 0};
-    const int m2 = centred_of(e, K);
-    if (gl < nlines && m2 >= -h && m2 < h) {
-      const int n0 = (int)(gl / N), n1 = (int)(gl % N), n2 = m2 + h;
-      const cx<T> xv = vol[gl * N + n2];
-      double f = s[n0] * s[n1] * s[n2];
-      if ((n0 + n1 + n2 + 3 * h) & 1) f = -f;
-      v.x = (T)((double)xv.x * f);
-      v.y = (T)((double)xv.y * f);
-    }
-    buf[fft::addr<true, L, NL>(line, e)] = v;
-  }
+  stage_tile<T, NL * L, NT>(
+      tid,
+      [&](int idx) {
+        const int line = idx / L, e = idx % L;
+        const int64_t gl = line0 + line;
+        cx<T> v = {0, 0};
+        const int m2 = centred_of(e, K);
+        if (gl < nlines && m2 >= -h && m2 < h) {
+          const int n0 = (int)(gl / N), n1 = (int)(gl % N), n2 = m2 + h;
+          const cx<T> xv = vol[gl * N + n2];
+          double f = s[n0] * s[n1] * s[n2];
+          if ((n0 + n1 + n2 + 3 * h) & 1) f = -f;
+          v.x = (T)((double)xv.x * f);
+          v.y = (T)((double)xv.y * f);
+        }
+        return v;
+      },
+      [&](int idx, cx<T> v) { buf[fft::addr<true, L, NL>(idx / L, idx % L)] = v; });
   __syncthreads();
   fft::run<T, L, NL, NT, true, -1>(buf, twp, tid);
   for (int idx = tid; idx < NL * L; idx += NT) {
@@ -174,18 +205,21 @@ __global__ __launch_bounds__(NTS) void k_fft_strided(cx<T>* __restrict__ grid,
     }
     return;
   }
-  for (int idx = tid; idx < NL * L; idx += NTS) {
-    const int line = idx % NL, e = idx / NL;
-    cx<T> v = {0, 0};
-    const int m = centred_of(e, K);
-    bool ld = !load_pruned || (m >= -h && m < h);
-    if (ball == 2) {
-      const double kr = (double)(e - K / 2), kc = (double)(col0 + line - K / 2);
-      ld = ld && kr * kr + ko * ko + kc * kc <= r2;
-    }
-    if (ld) v = base[e * row_stride + line];
-    buf[idx] = v;  // column-major address e*NL + line
-  }
+  stage_tile<T, NL * L, NTS>(
+      tid,
+      [&](int idx) {
+        const int line = idx % NL, e = idx / NL;
+        cx<T> v = {0, 0};
+        const int m = centred_of(e, K);
+        bool ld = !load_pruned || (m >= -h && m < h);
+        if (ball == 2) {
+          const double kr = (double)(e - K / 2), kc = (double)(col0 + line - K / 2);
+          ld = ld && kr * kr + ko * ko + kc * kc <= r2;
+        }
+        if (ld) v = base[e * row_stride + line];
+        return v;
+      },
+      [&](int idx, cx<T> v) { buf[idx] = v; });  // column-major address e*NL + line
   __syncthreads();
   fft::run<T, L, NL, NTS, false, S>(buf, twp, tid);
   for (int idx = tid; idx < NL * L; idx += NTS) {
@@ -221,17 +255,20 @@ __global__ __launch_bounds__(NT) void k_ifft_crop_x(const cx<T>* __restrict__ gr
   const int64_t nlines = (int64_t)N * N;
   const int64_t line0 = (int64_t)blockIdx.x * NL;
   const int h = N / 2;
-  for (int idx = tid; idx < NL * L; idx += NT) {
-    const int line = idx / L, e = idx % L;
-    const int64_t gl = line0 + line;
-    cx<T> v = {0, 0};
-    if (gl < nlines) {
-      const int n0 = (int)(gl / N), n1 = (int)(gl % N);
-      const int q0 = wrap_of(n0 - h, K), q1 = wrap_of(n1 - h, K);
-      v = grid[((int64_t)q0 * K + q1) * K + e];
-    }
-    buf[fft::addr<true, L, NL>(line, e)] = v;
-  }
+  stage_tile<T, NL * L, NT>(
+      tid,
+      [&](int idx) {
+        const int line = idx / L, e = idx % L;
+        const int64_t gl = line0 + line;
+        cx<T> v = {0, 0};
+        if (gl < nlines) {
+          const int n0 = (int)(gl / N), n1 = (int)(gl % N);
+          const int q0 = wrap_of(n0 - h, K), q1 = wrap_of(n1 - h, K);
+          v = grid[((int64_t)q0 * K + q1) * K + e];
+        }
+        return v;
+      },
+      [&](int idx, cx<T> v) { buf[fft::addr<true, L, NL>(idx / L, idx % L)] = v; });
   __syncthreads();
   fft::run<T, L, NL, NT, true, +1>(buf, twp, tid);
   for (int idx = tid; idx < NL * N; idx += NT) {
@@ -275,20 +312,23 @@ __global__ __launch_bounds__(NT) void k_radial(const cx<T>* __restrict__ in,
   const int tid = threadIdx.x;
   const int64_t line0 = (int64_t)blockIdx.x * NL;
   const T post = (T)(((L / 2) & 1 ? -1.0 : 1.0) / (double)L);
-  for (int idx = tid; idx < NL * L; idx += NT) {
-    const int line = idx / L, e = idx % L;
-    const int64_t gl = line0 + line;
-    cx<T> v = {0, 0};
-    if (gl < nlines) {
-      v = in[gl * L + e];
-      if (!ADJ && deriv) {  // multiply by f_c = i r_c, f_0 = 0
-        const T r = e == 0 ? (T)0 : (T)((double)(e - L / 2) * dr);
-        v = cx<T>{-r * v.y, r * v.x};
-      }
-      if (e & 1) v = cx<T>{-v.x, -v.y};
-    }
-    buf[fft::addr<true, L, NL>(line, e)] = v;
-  }
+  stage_tile<T, NL * L, NT>(
+      tid,
+      [&](int idx) {
+        const int line = idx / L, e = idx % L;
+        const int64_t gl = line0 + line;
+        cx<T> v = {0, 0};
+        if (gl < nlines) {
+          v = in[gl * L + e];
+          if (!ADJ && deriv) {  // multiply by f_c = i r_c, f_0 = 0
+            const T r = e == 0 ? (T)0 : (T)((double)(e - L / 2) * dr);
+            v = cx<T>{-r * v.y, r * v.x};
+          }
+          if (e & 1) v = cx<T>{-v.x, -v.y};
+        }
+        return v;
+      },
+      [&](int idx, cx<T> v) { buf[fft::addr<true, L, NL>(idx / L, idx % L)] = v; });
   __syncthreads();
   fft::run<T, L, NL, NT, true, ADJ ? -1 : +1>(buf, twp, tid);
   for (int idx = tid; idx < NL * L; idx += NT) {
