@@ -23,6 +23,7 @@
 #include "cx.h"
 #include "fft_lds.h"
 #include "plan.h"
+#include "stage.h"
 
 #ifndef NUFFTCT_FFT_TW_LDS
 #define NUFFTCT_FFT_TW_LDS 1
@@ -59,33 +60,6 @@ constexpr int nl_col() {  // columns per tile for strided passes
 
 __device__ __forceinline__ int centred_of(int e, int K) { return e < K / 2 ? e : e - K; }
 
-// Staging of a tile of NE elements by NTH threads: thread t handles elements
-// t, t + NTH, ...  All of its loads are issued before any is written to LDS,
-// so that they are in flight together (a loop that writes each element as it
-// arrives keeps one load per thread in flight and leaves the pass bound by
-// memory latency rather than bandwidth).
-#ifndef NUFFTCT_FFT_BATCH_LOADS
-#define NUFFTCT_FFT_BATCH_LOADS 1
-#endif
-template <typename T, int NE, int NTH, typename Ld, typename St>
-__device__ __forceinline__ void stage_tile(int tid, Ld&& ld, St&& st) {
-#if NUFFTCT_FFT_BATCH_LOADS
-  constexpr int PER = (NE + NTH - 1) / NTH;
-  cx<T> v[PER];
-#pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    const int idx = tid + k * NTH;
-    v[k] = (NE % NTH == 0 || idx < NE) ? ld(idx) : cx<T>{0, 0};
-  }
-#pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    const int idx = tid + k * NTH;
-    if (NE % NTH == 0 || idx < NE) st(idx, v[k]);
-  }
-#else
-  for (int idx = tid; idx < NE; idx += NTH) st(idx, ld(idx));
-#endif
-}
 __device__ __forceinline__ int wrap_of(int m, int K) { return m >= 0 ? m : m + K; }
 
 // ---------------------------------------------------------------------------
@@ -109,7 +83,7 @@ __global__ __launch_bounds__(NT) void k_pad_fft_x(const cx<T>* __restrict__ vol,
   const int64_t nlines = (int64_t)N * N;
   const int64_t line0 = (int64_t)blockIdx.x * NL;
   const int h = N / 2;
-  stage_tile<T, NL * L, NT>(
+  stage::tile<T, NL * L, NT>(
       tid,
       [&](int idx) {
         const int line = idx / L, e = idx % L;
@@ -205,7 +179,7 @@ __global__ __launch_bounds__(NTS) void k_fft_strided(cx<T>* __restrict__ grid,
     }
     return;
   }
-  stage_tile<T, NL * L, NTS>(
+  stage::tile<T, NL * L, NTS>(
       tid,
       [&](int idx) {
         const int line = idx % NL, e = idx / NL;
@@ -255,7 +229,7 @@ __global__ __launch_bounds__(NT) void k_ifft_crop_x(const cx<T>* __restrict__ gr
   const int64_t nlines = (int64_t)N * N;
   const int64_t line0 = (int64_t)blockIdx.x * NL;
   const int h = N / 2;
-  stage_tile<T, NL * L, NT>(
+  stage::tile<T, NL * L, NT>(
       tid,
       [&](int idx) {
         const int line = idx / L, e = idx % L;
@@ -312,7 +286,7 @@ __global__ __launch_bounds__(NT) void k_radial(const cx<T>* __restrict__ in,
   const int tid = threadIdx.x;
   const int64_t line0 = (int64_t)blockIdx.x * NL;
   const T post = (T)(((L / 2) & 1 ? -1.0 : 1.0) / (double)L);
-  stage_tile<T, NL * L, NT>(
+  stage::tile<T, NL * L, NT>(
       tid,
       [&](int idx) {
         const int line = idx / L, e = idx % L;

@@ -197,6 +197,10 @@ __device__ __forceinline__ int round_int(float x) {
 #endif
 }
 
+#ifndef NUFFTCT_INTERP_STAGE_CH
+#define NUFFTCT_INTERP_STAGE_CH 8
+#endif
+
 // Innermost pitch of the interpolation's staged halo tile: for FP32, S rounded
 // up to even, so that a row's start parity equals its first tap's parity and
 // pairs of complex values can be read as aligned 16-byte words.
@@ -324,10 +328,31 @@ __attribute__((amdgpu_waves_per_eu(NUFFTCT_INTERP_WAVES_PER_EU))) void k_interp(
   const int K = g.K;
   const int b2 = tk.bin % nb, b1 = (tk.bin / nb) % nb, b0 = tk.bin / (nb * nb);
   const int o0 = b0 * TILE, o1 = b1 * TILE, o2 = b2 * TILE;
-  for (int idx = threadIdx.x; idx < S * S * S; idx += NT_INTERP) {
-    const int i2 = idx % S, i1 = (idx / S) % S, i0 = idx / (S * S);
-    const int c0 = wrapK(o0 + i0, K), c1 = wrapK(o1 + i1, K), c2 = wrapK(o2 + i2, K);
-    tile[(i0 * S + i1) * S2 + i2] = grid[((int64_t)c0 * K + c1) * K + c2];
+  {
+    // CH loads per thread in flight before their LDS writes (a loop that
+    // writes each cell as it arrives waits on every load in turn)
+    constexpr int NE = S * S * S, CH = NUFFTCT_INTERP_STAGE_CH;
+#pragma unroll 1
+    for (int i = threadIdx.x; i < NE; i += CH * NT_INTERP) {
+      cx<T> v[CH];
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        const int idx = i + k * NT_INTERP;
+        if (idx < NE) {
+          const int i2 = idx % S, i1 = (idx / S) % S, i0 = idx / (S * S);
+          const int c0 = wrapK(o0 + i0, K), c1 = wrapK(o1 + i1, K), c2 = wrapK(o2 + i2, K);
+          v[k] = grid[((int64_t)c0 * K + c1) * K + c2];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        const int idx = i + k * NT_INTERP;
+        if (idx < NE) {
+          const int i2 = idx % S, i1 = (idx / S) % S, i0 = idx / (S * S);
+          tile[(i0 * S + i1) * S2 + i2] = v[k];
+        }
+      }
+    }
   }
   __syncthreads();
 #if NUFFTCT_INTERP_PREFETCH == 1
@@ -432,9 +457,20 @@ __attribute__((amdgpu_waves_per_eu(NUFFTCT_SPREAD_WAVES_PER_EU))) void k_spread(
     if (threadIdx.x == 0) s_maxbits = 0u;
     __syncthreads();
     float m = 0.f;
-    for (int i = threadIdx.x; i < tk.count; i += NT_SPREAD) {
-      const cx<T> v = in[perm[tk.start + i]];
-      m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+    // four points per step, so that four dependent load pairs are in flight
+    for (int i0 = threadIdx.x; i0 < tk.count; i0 += 4 * NT_SPREAD) {
+      int id[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int i = i0 + k * NT_SPREAD;
+        id[k] = i < tk.count ? perm[tk.start + i] : -1;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (id[k] >= 0) {
+          const cx<T> v = in[id[k]];
+          m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+        }
     }
     // non-negative floats order like their bit patterns
     atomicMax(&s_maxbits, __float_as_uint(m));
