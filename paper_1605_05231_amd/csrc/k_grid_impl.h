@@ -774,25 +774,27 @@ __global__ __launch_bounds__(1024) void k_merge_pairs(const cx<float>* __restric
       e2s[delta] = e2;
       off[delta] = part_base(delta, TILE, R) + (i0 * e1 + i1) * e2 + i2;
     }
+    // every load is issued unconditionally (masked-off lanes read element 0
+    // and drop it), so that all of them are in flight together: loads under
+    // divergent branches are waited for where the branches join
     cx<float> f[8][C];
 #pragma unroll
     for (int delta = 0; delta < 8; ++delta) {
-#pragma unroll
-      for (int q = 0; q < C; ++q) f[delta][q] = cx<float>{0, 0};
-      const int64_t o = rng[2 * delta] * PS + off[delta];
+      const int64_t o = any[delta] ? rng[2 * delta] * PS + off[delta] : 0;
       if ((delta & 1) == 0) {  // rows of TILE cells: 16-byte reads of cell pairs
-        if (any[delta]) {
 #pragma unroll
-          for (int q = 0; q < C; q += 2) {
-            const float4 v = p4[(o + q) >> 1];
-            f[delta][q] = cx<float>{v.x, v.y};
-            f[delta][q + 1] = cx<float>{v.z, v.w};
-          }
+        for (int q = 0; q < C; q += 2) {
+          const float4 v = p4[(o + q) >> 1];
+          f[delta][q] = any[delta] ? cx<float>{v.x, v.y} : cx<float>{0, 0};
+          f[delta][q + 1] = any[delta] ? cx<float>{v.z, v.w} : cx<float>{0, 0};
         }
       } else {
 #pragma unroll
-        for (int q = 0; q < C; ++q)
-          if (any[delta] && i2 + q < e2s[delta]) f[delta][q] = partials[o + q];
+        for (int q = 0; q < C; ++q) {
+          const bool ok = any[delta] && i2 + q < e2s[delta];
+          const cx<float> v = partials[ok ? o + q : 0];
+          f[delta][q] = ok ? v : cx<float>{0, 0};
+        }
       }
     }
 #pragma unroll
