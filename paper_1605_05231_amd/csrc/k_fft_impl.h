@@ -91,7 +91,7 @@ __global__ __launch_bounds__(NT) void k_pad_fft_x(const cx<T>* __restrict__ vol,
         cx<T> v = {0, 0};
         const int m2 = centred_of(e, K);
         if (gl < nlines && m2 >= -h && m2 < h) {
-          const int n0 = (int)(gl / N), n1 = (int)(gl % N), n2 = m2 + h;
+          const int n0 = (int)gl / N, n1 = (int)gl % N, n2 = m2 + h;  // N^2 < 2^31
           const cx<T> xv = vol[gl * N + n2];
           double f = s[n0] * s[n1] * s[n2];
           if ((n0 + n1 + n2 + 3 * h) & 1) f = -f;
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(NT) void k_pad_fft_x(const cx<T>* __restrict__ vol,
     const int line = idx / L, e = idx % L;
     const int64_t gl = line0 + line;
     if (gl < nlines) {
-      const int n0 = (int)(gl / N), n1 = (int)(gl % N);
+      const int n0 = (int)gl / N, n1 = (int)gl % N;
       const int q0 = wrap_of(n0 - h, K), q1 = wrap_of(n1 - h, K);
       grid[((int64_t)q0 * K + q1) * K + e] = buf[fft::addr<true, L, NL>(line, e)];
     }
@@ -236,7 +236,7 @@ __global__ __launch_bounds__(NT) void k_ifft_crop_x(const cx<T>* __restrict__ gr
         const int64_t gl = line0 + line;
         cx<T> v = {0, 0};
         if (gl < nlines) {
-          const int n0 = (int)(gl / N), n1 = (int)(gl % N);
+          const int n0 = (int)gl / N, n1 = (int)gl % N;
           const int q0 = wrap_of(n0 - h, K), q1 = wrap_of(n1 - h, K);
           v = grid[((int64_t)q0 * K + q1) * K + e];
         }
@@ -249,7 +249,7 @@ __global__ __launch_bounds__(NT) void k_ifft_crop_x(const cx<T>* __restrict__ gr
     const int line = idx / N, n2 = idx % N;
     const int64_t gl = line0 + line;
     if (gl < nlines) {
-      const int n0 = (int)(gl / N), n1 = (int)(gl % N);
+      const int n0 = (int)gl / N, n1 = (int)gl % N;
       const int e = wrap_of(n2 - h, K);
       const cx<T> v = buf[fft::addr<true, L, NL>(line, e)];
       double f = s[n0] * s[n1] * s[n2];
