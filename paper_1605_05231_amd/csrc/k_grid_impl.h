@@ -406,6 +406,71 @@ __attribute__((amdgpu_waves_per_eu(NUFFTCT_INTERP_WAVES_PER_EU))) void k_interp(
   }
 }
 
+// One contribution u to halo cell `cell` of the task's LDS accumulators:
+// FP32 packs the rounded components into one 64-bit word (q_re 2^32 + q_im,
+// the high half less the borrow of a negative q_im); FP64 adds to planar
+// accumulators.
+template <typename T, int SS>
+__device__ __forceinline__ void add_cell(unsigned long long* accp, double* acc, int cell, cx<T> u) {
+  if constexpr (sizeof(T) == 4) {
+    const int qr = round_int(u.x), qi = round_int(u.y);
+    const unsigned int hi = (unsigned int)qr + (unsigned int)(qi >> 31);
+    lds_add(&accp[cell], ((unsigned long long)hi << 32) | (unsigned int)qi);
+  } else {
+    lds_add(&acc[cell], (double)u.x);
+    lds_add(&acc[SS + cell], (double)u.y);
+  }
+}
+
+// The J^3 contributions of one point (value v, tap (0,0,0) at halo cell
+// `base`), with conj(w) for the transpose.
+template <typename T, int J, int S, int SS, bool CW>
+__device__ __forceinline__ void spread_one(unsigned long long* accp, double* acc, cx<T> v, int base,
+                                           const T (&w0r)[J], const T (&w0i)[J],
+                                           const T (&w1r)[J], const T (&w1i)[J],
+                                           const T (&w2r)[J], const T (&w2i)[J]) {
+#pragma unroll
+  for (int a = 0; a < J; ++a) {
+    const cx<T> va = CW ? cmulc(v, cx<T>{w0r[a], w0i[a]}) : cx<T>{w0r[a] * v.x, w0r[a] * v.y};
+#pragma unroll
+    for (int b = 0; b < J; ++b) {
+      const cx<T> vb =
+          CW ? cmulc(va, cx<T>{w1r[b], w1i[b]}) : cx<T>{w1r[b] * va.x, w1r[b] * va.y};
+      const int row = base + (a * S + b) * S;
+#pragma unroll
+      for (int c = 0; c < J; ++c) {
+        const cx<T> u =
+            CW ? cmulc(vb, cx<T>{w2r[c], w2i[c]}) : cx<T>{w2r[c] * vb.x, w2r[c] * vb.y};
+        add_cell<T, SS>(accp, acc, row + c, u);
+      }
+    }
+  }
+}
+
+// Two points with the same first tap cell and real weights w and x: each of
+// the J^3 cells receives w v + x v2 in one atomic.
+template <typename T, int J, int S, int SS>
+__device__ __forceinline__ void spread_pair(unsigned long long* accp, double* acc, cx<T> v,
+                                            cx<T> v2, int base, const T (&w0r)[J],
+                                            const T (&w1r)[J], const T (&w2r)[J],
+                                            const T (&x0r)[J], const T (&x1r)[J],
+                                            const T (&x2r)[J]) {
+#pragma unroll
+  for (int a = 0; a < J; ++a) {
+    const cx<T> va = {w0r[a] * v.x, w0r[a] * v.y}, xa = {x0r[a] * v2.x, x0r[a] * v2.y};
+#pragma unroll
+    for (int b = 0; b < J; ++b) {
+      const cx<T> vb = {w1r[b] * va.x, w1r[b] * va.y}, xb = {x1r[b] * xa.x, x1r[b] * xa.y};
+      const int row = base + (a * S + b) * S;
+#pragma unroll
+      for (int c = 0; c < J; ++c) {
+        const cx<T> u = {w2r[c] * vb.x + x2r[c] * xb.x, w2r[c] * vb.y + x2r[c] * xb.y};
+        add_cell<T, SS>(accp, acc, row + c, u);
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Spreading, phase 1: one workgroup per task accumulates all J^3 taps of its
 // points into the task's halo tile (S^3 cells, S = TILE + J - 1) in LDS, then
@@ -481,57 +546,81 @@ __attribute__((amdgpu_waves_per_eu(NUFFTCT_SPREAD_WAVES_PER_EU))) void k_spread(
   } else {
     __syncthreads();
   }
-  PtRaw nxt;
-  cx<T> vnxt = {0, 0};
-  if ((int)threadIdx.x < tk.count) {
-    nxt = fetch_point(g, perm, tk.start + threadIdx.x);
+  // units: a pair of points that share their first tap cell (entries 2u and
+  // 2u + 1, u < npairs), then single points (entry npairs + u)
+  // FP32 with real weights: both points' contributions to a cell summed
+  // before one atomic; otherwise (min-max weights, or FP64, whose register
+  // budget it would exceed) the points of a unit are spread one by one
+  constexpr bool PAIRED = !CW && sizeof(T) == 4;
+  const int np = tk.npairs, nunits = tk.count - np;
+  PtRaw nxt, nxt2;
+  cx<T> vnxt = {0, 0}, vnxt2 = {0, 0};
+  auto fetch_unit = [&](int u) {  // one unit ahead (its second point if paired)
+    const int e = u < np ? 2 * u : np + u;
+    nxt = fetch_point(g, perm, tk.start + e);
     vnxt = in[nxt.p];
-  }
-  for (int i = threadIdx.x; i < tk.count; i += NT_SPREAD) {
-    const PtRaw cur = nxt;
-    cx<T> v = vnxt;
-    if (i + NT_SPREAD < tk.count) {
-      nxt = fetch_point(g, perm, tk.start + i + NT_SPREAD);
-      vnxt = in[nxt.p];
+    vnxt2 = cx<T>{0, 0};
+    if (PAIRED && u < np) {
+      nxt2 = fetch_point(g, perm, tk.start + e + 1);
+      vnxt2 = in[nxt2.p];
+    }
+  };
+  if ((int)threadIdx.x < nunits) fetch_unit(threadIdx.x);
+  for (int u = threadIdx.x; u < nunits; u += NT_SPREAD) {
+    PtRaw cur = nxt, cur2 = nxt2;
+    cx<T> v = vnxt, v2 = vnxt2;
+    const bool pair = u < np;
+    if (u + NT_SPREAD < nunits) fetch_unit(u + NT_SPREAD);
+    if (!PAIRED && pair) {
+      cur2 = fetch_point(g, perm, tk.start + 2 * u + 1);
+      v2 = in[cur2.p];
     }
     v = cx<T>{v.x * scale, v.y * scale};
-    int first[3];
-    double frac[3];
+    v2 = cx<T>{v2.x * scale, v2.y * scale};
+    int first[3], first2[3] = {0, 0, 0};
+    double frac[3], frac2[3] = {0.0, 0.0, 0.0};
     point_taps<sizeof(T) == 4>(g, cur, J, first, frac);
     const int l0 = first[0] - o0, l1 = first[1] - o1, l2 = first[2] - o2;
     // the host bins with the same FP64 arithmetic, so every point of the task
     // lies in its tile; the check only keeps LDS accesses in bounds
-    if ((unsigned)l0 >= (unsigned)TILE || (unsigned)l1 >= (unsigned)TILE ||
-        (unsigned)l2 >= (unsigned)TILE)
-      continue;
+    const bool in1 = (unsigned)l0 < (unsigned)TILE && (unsigned)l1 < (unsigned)TILE &&
+                     (unsigned)l2 < (unsigned)TILE;
     T w0r[J], w0i[J], w1r[J], w1i[J], w2r[J], w2i[J];
     axis_weights<T, J, DEG, CW>(P, frac[0], w0r, w0i);
     axis_weights<T, J, DEG, CW>(P, frac[1], w1r, w1i);
     axis_weights<T, J, DEG, CW>(P, frac[2], w2r, w2i);
-#pragma unroll
-    for (int a = 0; a < J; ++a) {
-      // conj(w) for the transpose
-      const cx<T> va = CW ? cmulc(v, cx<T>{w0r[a], w0i[a]}) : cx<T>{w0r[a] * v.x, w0r[a] * v.y};
-#pragma unroll
-      for (int b = 0; b < J; ++b) {
-        const cx<T> vb =
-            CW ? cmulc(va, cx<T>{w1r[b], w1i[b]}) : cx<T>{w1r[b] * va.x, w1r[b] * va.y};
-        const int row = ((l0 + a) * S + (l1 + b)) * S + l2;
-#pragma unroll
-        for (int c = 0; c < J; ++c) {
-          const cx<T> u =
-              CW ? cmulc(vb, cx<T>{w2r[c], w2i[c]}) : cx<T>{w2r[c] * vb.x, w2r[c] * vb.y};
-          if constexpr (FIXED) {
-            // the word q_re 2^32 + q_im: low half q_im, high half q_re
-            // less the borrow of a negative q_im
-            const int qr = round_int(u.x), qi = round_int(u.y);
-            const unsigned int hi = (unsigned int)qr + (unsigned int)(qi >> 31);
-            lds_add(&accp[row + c], ((unsigned long long)hi << 32) | (unsigned int)qi);
-          } else {
-            lds_add(&acc[row + c], (double)u.x);
-            lds_add(&acc[SS + row + c], (double)u.y);
-          }
-        }
+    bool same = true;  // the second point shares the first tap cell
+    if (pair) {
+      point_taps<sizeof(T) == 4>(g, cur2, J, first2, frac2);
+      same = first2[0] == first[0] && first2[1] == first[1] && first2[2] == first[2];
+    }
+    if constexpr (PAIRED) {
+      // (a single point, or a pair whose first cells differ, adds a zero here)
+      T x0r[J], x0i[J], x1r[J], x1i[J], x2r[J], x2i[J];
+      const bool both = pair && same;
+      axis_weights<T, J, DEG, CW>(P, both ? frac2[0] : frac[0], x0r, x0i);
+      axis_weights<T, J, DEG, CW>(P, both ? frac2[1] : frac[1], x1r, x1i);
+      axis_weights<T, J, DEG, CW>(P, both ? frac2[2] : frac[2], x2r, x2i);
+      const cx<T> vq = both ? v2 : cx<T>{0, 0};
+      if (in1)
+        spread_pair<T, J, S, SS>(accp, acc, v, vq, (l0 * S + l1) * S + l2, w0r, w1r, w2r, x0r,
+                                 x1r, x2r);
+    } else {
+      if (in1)
+        spread_one<T, J, S, SS, CW>(accp, acc, v, (l0 * S + l1) * S + l2, w0r, w0i, w1r, w1i,
+                                    w2r, w2i);
+    }
+    if (pair && (!PAIRED || !same)) {
+      // the second point on its own (or first cells that differ in the
+      // device's rounding of a tie)
+      const int m0 = first2[0] - o0, m1 = first2[1] - o1, m2 = first2[2] - o2;
+      if ((unsigned)m0 < (unsigned)TILE && (unsigned)m1 < (unsigned)TILE &&
+          (unsigned)m2 < (unsigned)TILE) {
+        axis_weights<T, J, DEG, CW>(P, frac2[0], w0r, w0i);
+        axis_weights<T, J, DEG, CW>(P, frac2[1], w1r, w1i);
+        axis_weights<T, J, DEG, CW>(P, frac2[2], w2r, w2i);
+        spread_one<T, J, S, SS, CW>(accp, acc, v2, (m0 * S + m1) * S + m2, w0r, w0i, w1r, w1i,
+                                    w2r, w2i);
       }
     }
   }

@@ -115,9 +115,13 @@ struct Binning {
 // at most max_pts points.  Within a task the points are then ordered by the
 // LDS bank of their first tap's cell in the staged halo tile, once for each
 // of the two kernels that read the order:
-//   spreading: cell c = (l0 S + l1) S + l2 (S = tile + J - 1); points dealt
-//     round-robin over the residues c mod 32, so the lanes of a wave start
-//     on distinct banks and a tap offset shared by all lanes keeps them so;
+//   spreading: points that share their first tap cell are paired (one lane
+//     spreads both, summing their contributions to each of the J^3 cells
+//     before one LDS atomic); the pairs come first, then the unpaired
+//     points.  Cell c = (l0 S + l1) S + l2 (S = tile + J - 1); pairs, then
+//     singles, dealt round-robin over the residues c mod 32, so the lanes of
+//     a wave start on distinct banks and a tap offset shared by all lanes
+//     keeps them so;
 //   interpolation (FP32): rows padded to even pitch S2, cell
 //     c = (l0 S + l1) S2 + l2; even cells first, then odd ones (a wave's
 //     row reads then share one alignment), each class dealt round-robin over
@@ -131,6 +135,7 @@ static void build_bins(const nufftct_plan& p, const std::vector<double>& geom, B
   const int64_t nbins = (int64_t)nb * nb * nb;
   std::vector<int32_t> key(M);
   std::vector<uint8_t> res_s(M), res_i(M);
+  std::vector<uint16_t> lcell(M);  // first tap cell within its tile
   const double gamma = (2.0 * M_PI) / (double)p.K;
   unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   if (M < 200000) nth = 1;
@@ -149,6 +154,7 @@ static void build_bins(const nufftct_plan& p, const std::vector<double>& geom, B
       key[i] = (int32_t)(((int64_t)(first[0] / T) * nb + first[1] / T) * nb + first[2] / T);
       const int r01 = (first[0] % T) * S + first[1] % T;
       res_s[i] = (uint8_t)((r01 * S + first[2] % T) & 31);
+      lcell[i] = (uint16_t)(((first[0] % T) * T + first[1] % T) * T + first[2] % T);
       res_i[i] = (uint8_t)((r01 * S2 + first[2] % T) & 31);
     }
   });
@@ -170,7 +176,7 @@ static void build_bins(const nufftct_plan& p, const std::vector<double>& geom, B
       t.bin = (int32_t)b;
       t.start = (int32_t)q;
       t.count = (int32_t)std::min<int64_t>(p.max_pts, e - q);
-      t.pad = 0;
+      t.npairs = 0;
       B.tasks.push_back(t);
     }
   }
@@ -233,9 +239,39 @@ static void build_bins(const nufftct_plan& p, const std::vector<double>& geom, B
   };
   parallel((int64_t)B.tasks.size(), [&](int64_t a, int64_t b) {
     Deal d;
+    std::vector<int32_t> sorted, first_of, singles, idx;
+    std::vector<uint8_t> res_pair;
     for (int64_t k = a; k < b; ++k) {
-      const TileTask& t = B.tasks[k];
-      d.run(B.perm_s.data() + t.start, t.count, res_s.data(), 1);
+      TileTask& t = B.tasks[k];
+      int32_t* ps = B.perm_s.data() + t.start;
+      // pair the points of each first tap cell (in point order within it)
+      sorted.assign(ps, ps + t.count);
+      std::stable_sort(sorted.begin(), sorted.end(),
+                       [&](int32_t x, int32_t y) { return lcell[x] < lcell[y]; });
+      first_of.clear();
+      singles.clear();
+      res_pair.clear();
+      for (int i = 0; i < t.count;) {
+        int j = i;
+        while (j < t.count && lcell[sorted[j]] == lcell[sorted[i]]) ++j;
+        for (int q = i; q + 1 < j; q += 2) {
+          first_of.push_back(q);  // pair (sorted[q], sorted[q + 1])
+          res_pair.push_back(res_s[sorted[q]]);
+        }
+        if ((j - i) & 1) singles.push_back(sorted[j - 1]);
+        i = j;
+      }
+      const int np = (int)first_of.size();
+      idx.resize(np);
+      for (int q = 0; q < np; ++q) idx[q] = q;
+      d.run(idx.data(), np, res_pair.data(), 1);
+      for (int q = 0; q < np; ++q) {
+        ps[2 * q] = sorted[first_of[idx[q]]];
+        ps[2 * q + 1] = sorted[first_of[idx[q]] + 1];
+      }
+      d.run(singles.data(), (int)singles.size(), res_s.data(), 1);
+      std::copy(singles.begin(), singles.end(), ps + 2 * np);
+      t.npairs = np;
       d.run(B.perm.data() + t.start, t.count, pairs ? res_i.data() : res_s.data(), pairs ? 2 : 1);
     }
   });

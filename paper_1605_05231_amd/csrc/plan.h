@@ -37,10 +37,11 @@ struct PointGeom {
 };
 
 struct TileTask {
-  int32_t bin;    // linear tile index (b0 * nb + b1) * nb + b2
-  int32_t start;  // first entry in the permutation
-  int32_t count;  // number of points
-  int32_t pad;
+  int32_t bin;     // linear tile index (b0 * nb + b1) * nb + b2
+  int32_t start;   // first entry in the permutation
+  int32_t count;   // number of points
+  int32_t npairs;  // spreading order: its first 2 npairs entries are npairs
+                   // pairs of points that share their first tap cell
 };
 
 struct nufftct_plan {
