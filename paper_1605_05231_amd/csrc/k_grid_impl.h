@@ -39,6 +39,9 @@ namespace kgrid {
 #ifndef NUFFTCT_SPREAD_RPI
 #define NUFFTCT_SPREAD_RPI 1
 #endif
+#ifndef NUFFTCT_SPREAD_WRITE_PAIRS
+#define NUFFTCT_SPREAD_WRITE_PAIRS 1  // FP32 partial write-out: cell pairs, 16-byte stores
+#endif
 constexpr int NT = 256;
 constexpr int NT_INTERP = NUFFTCT_INTERP_NT;
 #ifndef NUFFTCT_SPREAD_NT
@@ -630,20 +633,41 @@ __attribute__((amdgpu_waves_per_eu(NUFFTCT_SPREAD_WAVES_PER_EU))) void k_spread(
   constexpr int R = J - 1;
   cx<T>* dst = partials + task_id * (int64_t)part_stride(TILE, R);
   const double inv = 1.0 / (double)scale;
+  auto decode = [&](unsigned long long w) {  // the two sums of a packed word
+    const long long lo = (long long)(int)(unsigned int)(w & 0xffffffffull);
+    const long long hi = (long long)(w - (unsigned long long)lo) >> 32;
+    return cx<T>{(T)((double)hi * inv), (T)((double)lo * inv)};
+  };
 #pragma unroll
   for (int delta = 0; delta < 8; ++delta) {
     const int d0 = (delta >> 2) & 1, d1 = (delta >> 1) & 1, d2 = delta & 1;
     const int e1 = part_ext(d1, TILE, R), e2 = part_ext(d2, TILE, R);
     const int n = part_size(delta, TILE, R), base = part_base(delta, TILE, R);
+    if constexpr (FIXED && NUFFTCT_SPREAD_WRITE_PAIRS) {
+      // blocks whose rows have an even length (and an even base): two cells
+      // of a row per lane, one 16-byte store
+      if ((e2 & 1) == 0) {
+        constexpr int NTS2 = NT_SPREAD;
+#pragma unroll
+        for (int k = 0; k < (part_size(delta, TILE, R) / 2 + NTS2 - 1) / NTS2; ++k) {
+          const int j = (int)threadIdx.x + k * NTS2;
+          if (j < n / 2) {
+            const int idx = 2 * j;
+            const int r2 = idx % e2, r1 = (idx / e2) % e1, r0 = idx / (e1 * e2);
+            const int cell = ((r0 + d0 * TILE) * S + (r1 + d1 * TILE)) * S + (r2 + d2 * TILE);
+            const cx<T> a = decode(accp[cell]), b = decode(accp[cell + 1]);
+            reinterpret_cast<float4*>(dst + base)[j] = make_float4(a.x, a.y, b.x, b.y);
+          }
+        }
+        continue;
+      }
+    }
     for (int idx = threadIdx.x; idx < n; idx += NT_SPREAD) {
       const int r2 = idx % e2, r1 = (idx / e2) % e1, r0 = idx / (e1 * e2);
       const int cell = ((r0 + d0 * TILE) * S + (r1 + d1 * TILE)) * S + (r2 + d2 * TILE);
       cx<T> v;
       if constexpr (FIXED) {
-        const unsigned long long w = accp[cell];
-        const long long lo = (long long)(int)(unsigned int)(w & 0xffffffffull);
-        const long long hi = (long long)(w - (unsigned long long)lo) >> 32;
-        v = cx<T>{(T)((double)hi * inv), (T)((double)lo * inv)};
+        v = decode(accp[cell]);
       } else {
         v = cx<T>{(T)acc[cell], (T)acc[SS + cell]};
       }
