@@ -118,7 +118,8 @@ struct Binning {
 //   spreading: points that share their first tap cell are paired (one lane
 //     spreads both, summing their contributions to each of the J^3 cells
 //     before one LDS atomic); the pairs come first, then the unpaired
-//     points.  Cell c = (l0 S + l1) S + l2 (S = tile + J - 1); pairs, then
+//     points (FP32 with Kaiser-Bessel weights; the other kernels spread one
+//     point at a time, and their tasks hold no pairs).  Cell c = (l0 S + l1) S + l2 (S = tile + J - 1); pairs, then
 //     singles, dealt round-robin over the residues c mod 32, so the lanes of
 //     a wave start on distinct banks and a tap offset shared by all lanes
 //     keeps them so;
@@ -131,6 +132,9 @@ static void build_bins(const nufftct_plan& p, const std::vector<double>& geom, B
   const int nb = p.nb, T = p.tile, J = p.J;
   const int S = T + J - 1;
   const bool pairs = p.precision == NUFFTCT_FP32;
+  // the FP32 spreading with Kaiser-Bessel weights sums paired points'
+  // contributions; the other kernels spread one point at a time
+  const bool pair_spread = pairs && p.kernel != NUFFTCT_KERNEL_MINMAX_KB;
   const int S2 = pairs ? S + (S & 1) : S;
   const int64_t nbins = (int64_t)nb * nb * nb;
   std::vector<int32_t> key(M);
@@ -244,6 +248,12 @@ static void build_bins(const nufftct_plan& p, const std::vector<double>& geom, B
     for (int64_t k = a; k < b; ++k) {
       TileTask& t = B.tasks[k];
       int32_t* ps = B.perm_s.data() + t.start;
+      if (!pair_spread) {  // no paired spreading: points dealt one by one
+        d.run(ps, t.count, res_s.data(), 1);
+        t.npairs = 0;
+        d.run(B.perm.data() + t.start, t.count, pairs ? res_i.data() : res_s.data(), pairs ? 2 : 1);
+        continue;
+      }
       // pair the points of each first tap cell (in point order within it)
       sorted.assign(ps, ps + t.count);
       std::stable_sort(sorted.begin(), sorted.end(),
