@@ -5,8 +5,7 @@ import ctypes as C
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# NUFFTCT_LIB may point at another build of the same library (kernel-variant sweeps)
-LIB_PATH = os.environ.get("NUFFTCT_LIB") or os.path.join(_HERE, "libnufftct.so")
+LIB_PATH = os.path.join(_HERE, "libnufftct.so")
 
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, 1, 2, 3, 4
 KERNEL_KB, KERNEL_MINMAX_KB = 0, 1

@@ -12,13 +12,11 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libnufftct.so")
 BUILD = os.path.join(ROOT, "_build")
-# extra compile definitions for kernel-variant sweeps, e.g. "-DNUFFTCT_INTERP_NT=512"
-EXTRA = os.environ.get("NUFFTCT_EXTRA_FLAGS", "").split()
 
 SOURCES = ["plan.cpp", "tables.cpp", "batch.cpp", "umbrella.cpp", "k_fft_f32.hip", "k_fft_f64.hip",
            "k_grid_f32.hip", "k_grid_f64.hip", "k_umbrella.hip"]
 
-ARCH = os.environ.get("NUFFTCT_ARCH", "gfx950")
+ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           # packed FP32 instructions are disabled for every HIP translation unit
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -36,7 +34,7 @@ def hipcc() -> str:
 
 def _compile(src: str, verbose: bool, build_dir: str) -> str:
     obj = os.path.join(build_dir, src + ".o")
-    cmd = [hipcc(), "-c", os.path.join(CSRC, src), "-o", obj] + COMMON + EXTRA + HOST_ONLY.get(src, [])
+    cmd = [hipcc(), "-c", os.path.join(CSRC, src), "-o", obj] + COMMON + HOST_ONLY.get(src, [])
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     if verbose:

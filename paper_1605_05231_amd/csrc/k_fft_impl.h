@@ -25,23 +25,10 @@
 #include "plan.h"
 #include "stage.h"
 
-#ifndef NUFFTCT_FFT_TW_LDS
-#define NUFFTCT_FFT_TW_LDS 1
-#endif
-#ifndef NUFFTCT_FFT_XCD_COLS
-#define NUFFTCT_FFT_XCD_COLS 1
-#endif
-
 namespace kfft {
 
-#ifndef NUFFTCT_FFT_LINE_NT
-#define NUFFTCT_FFT_LINE_NT 512
-#endif
-constexpr int NT = NUFFTCT_FFT_LINE_NT;  // threads of a line-major workgroup
-#ifndef NUFFTCT_FFT_STRIDED_NT
-#define NUFFTCT_FFT_STRIDED_NT 1024
-#endif
-constexpr int NTS = NUFFTCT_FFT_STRIDED_NT;  // threads of a strided-pass workgroup
+constexpr int NT = 512;    // threads of a line-major workgroup
+constexpr int NTS = 1024;  // threads of a strided-pass workgroup
 
 template <typename T, int L>
 constexpr int nl_line() {  // lines per tile for line-major passes
@@ -49,12 +36,11 @@ constexpr int nl_line() {  // lines per tile for line-major passes
   return target / L > 0 ? target / L : 1;
 }
 
-#ifndef NUFFTCT_FFT_COLS_F32
-#define NUFFTCT_FFT_COLS_F32 16
-#endif
+// columns per tile for strided passes: FP32 16 adjacent columns (128-byte row
+// segments); 8 or 32 measured slower
 template <typename T, int L>
-constexpr int nl_col() {  // columns per tile for strided passes
-  if constexpr (sizeof(T) == 4) return L <= 512 ? NUFFTCT_FFT_COLS_F32 : 8;
+constexpr int nl_col() {
+  if constexpr (sizeof(T) == 4) return L <= 512 ? 16 : 8;
   return L <= 512 ? 8 : 4;
 }
 
@@ -72,13 +58,9 @@ __global__ __launch_bounds__(NT) void k_pad_fft_x(const cx<T>* __restrict__ vol,
   constexpr int NL = nl_line<T, L>();
   constexpr int K = L;
   __shared__ cx<T> buf[fft::tile_elems<true, L, NL>()];
-#if NUFFTCT_FFT_TW_LDS
   __shared__ cx<T> twl[L];
   for (int i = threadIdx.x; i < L; i += NT) twl[i] = tw[i];
   const cx<T>* twp = twl;
-#else
-  const cx<T>* twp = tw;
-#endif
   const int tid = threadIdx.x;
   const int64_t nlines = (int64_t)N * N;
   const int64_t line0 = (int64_t)blockIdx.x * NL;
@@ -136,20 +118,15 @@ __global__ __launch_bounds__(NTS) void k_fft_strided(cx<T>* __restrict__ grid,
   constexpr int NL = nl_col<T, L>();
   constexpr int K = L;
   __shared__ cx<T> buf[fft::tile_elems<false, L, NL>()];
-#if NUFFTCT_FFT_TW_LDS
   // the twiddle table in LDS: every stage's twiddle reads become LDS reads
   // (broadcast across the columns of a butterfly row)
   __shared__ cx<T> twl[L];
   for (int i = threadIdx.x; i < L; i += NTS) twl[i] = tw[i];
   const cx<T>* twp = twl;
-#else
-  const cx<T>* twp = tw;
-#endif
   const int tid = threadIdx.x;
   const int h = N / 2;
   const int o = blockIdx.y;
   const int qo = outer_pruned ? wrap_of(o - h, K) : o;
-#if NUFFTCT_FFT_XCD_COLS
   // workgroups go round-robin over the 8 XCDs: give each XCD a contiguous
   // run of column groups, so that the groups sharing a cache line of a row
   // meet in one L2
@@ -157,9 +134,6 @@ __global__ __launch_bounds__(NTS) void k_fft_strided(cx<T>* __restrict__ grid,
   if ((gridDim.x & (NUFFTCT_NUM_XCD - 1)) == 0)
     cg = (cg % NUFFTCT_NUM_XCD) * (gridDim.x / NUFFTCT_NUM_XCD) + cg / NUFFTCT_NUM_XCD;
   const int col0 = cg * NL;
-#else
-  const int col0 = blockIdx.x * NL;
-#endif
   cx<T>* base = grid + (int64_t)qo * outer_stride + col0;
   // squared distance of this block's nearest column from the ball's axis
   const double ko = outer_in_ball ? (double)(qo - K / 2) : 0.0;
@@ -218,13 +192,9 @@ __global__ __launch_bounds__(NT) void k_ifft_crop_x(const cx<T>* __restrict__ gr
   constexpr int NL = nl_line<T, L>();
   constexpr int K = L;
   __shared__ cx<T> buf[fft::tile_elems<true, L, NL>()];
-#if NUFFTCT_FFT_TW_LDS
   __shared__ cx<T> twl[L];
   for (int i = threadIdx.x; i < L; i += NT) twl[i] = tw[i];
   const cx<T>* twp = twl;
-#else
-  const cx<T>* twp = tw;
-#endif
   const int tid = threadIdx.x;
   const int64_t nlines = (int64_t)N * N;
   const int64_t line0 = (int64_t)blockIdx.x * NL;
@@ -276,13 +246,9 @@ __global__ __launch_bounds__(NT) void k_radial(const cx<T>* __restrict__ in,
                                                double w_scale) {
   constexpr int NL = nl_line<T, L>();
   __shared__ cx<T> buf[fft::tile_elems<true, L, NL>()];
-#if NUFFTCT_FFT_TW_LDS
   __shared__ cx<T> twl[L];
   for (int i = threadIdx.x; i < L; i += NT) twl[i] = tw[i];
   const cx<T>* twp = twl;
-#else
-  const cx<T>* twp = tw;
-#endif
   const int tid = threadIdx.x;
   const int64_t line0 = (int64_t)blockIdx.x * NL;
   const T post = (T)(((L / 2) & 1 ? -1.0 : 1.0) / (double)L);

@@ -27,30 +27,28 @@
 
 namespace kgrid {
 
-#ifndef NUFFTCT_INTERP_NT
-#define NUFFTCT_INTERP_NT 256
-#endif
-#ifndef NUFFTCT_INTERP_PREFETCH
-#define NUFFTCT_INTERP_PREFETCH 1
-#endif
-#ifndef NUFFTCT_INTERP_WAVES_PER_EU
-#define NUFFTCT_INTERP_WAVES_PER_EU 1
-#endif
-#ifndef NUFFTCT_SPREAD_RPI
-#define NUFFTCT_SPREAD_RPI 1
-#endif
-#ifndef NUFFTCT_SPREAD_WRITE_PAIRS
-#define NUFFTCT_SPREAD_WRITE_PAIRS 1  // FP32 partial write-out: cell pairs, 16-byte stores
-#endif
-constexpr int NT = 256;
-constexpr int NT_INTERP = NUFFTCT_INTERP_NT;
-#ifndef NUFFTCT_SPREAD_NT
-#define NUFFTCT_SPREAD_NT 1024
-#endif
-#ifndef NUFFTCT_SPREAD_WAVES_PER_EU
-#define NUFFTCT_SPREAD_WAVES_PER_EU 1
-#endif
-constexpr int NT_SPREAD = NUFFTCT_SPREAD_NT;
+// Launch shapes per precision (measured on gfx950):
+//   FP32 interpolation: two 512-thread workgroups per CU (LDS-bound) within
+//     128 VGPRs, which leaves room for a one-ahead prefetch of the next
+//     point's id only (not of its geometry);
+//   FP32 spreading: one 8-byte accumulator per halo cell (74 KB for tile 16,
+//     J = 6), so two 512-thread workgroups share a CU within 128 VGPRs;
+//   FP64: 256-thread interpolation with the next point's geometry prefetched,
+//     1024-thread spreading.
+template <typename T>
+struct GridCfg;
+template <>
+struct GridCfg<float> {
+  static constexpr int NT_INTERP = 512, INTERP_WAVES = 4, NT_SPREAD = 512, SPREAD_WAVES = 4;
+  static constexpr bool PREFETCH_GEOM = false;
+};
+template <>
+struct GridCfg<double> {
+  static constexpr int NT_INTERP = 256, INTERP_WAVES = 1, NT_SPREAD = 1024, SPREAD_WAVES = 1;
+  static constexpr bool PREFETCH_GEOM = true;
+};
+// threads of the plan-time spreading-bound kernel (FP32 plans only)
+constexpr int NT_BOUND = 512;
 
 template <typename T>
 __device__ __forceinline__ void lds_add(T* a, T v) {
@@ -191,18 +189,10 @@ __device__ __forceinline__ int wrapK(int c, int K) { return c >= K ? c - K : c; 
 // floor(x + 1/2) as a 32-bit integer in one instruction (|x| < 2^31); the
 // compiler's round-to-nearest conversion takes two
 __device__ __forceinline__ int round_int(float x) {
-#if NUFFTCT_SPREAD_RPI
   int r;
   asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
   return r;
-#else
-  return __float2int_rn(x);
-#endif
 }
-
-#ifndef NUFFTCT_INTERP_STAGE_CH
-#define NUFFTCT_INTERP_STAGE_CH 8
-#endif
 
 // Innermost pitch of the interpolation's staged halo tile: for FP32, S rounded
 // up to even, so that a row's start parity equals its first tap's parity and
@@ -234,14 +224,6 @@ __device__ __forceinline__ void read_row(const cx<T>* tile, int rs, cx<T> (&v)[J
   }
 }
 
-// Unroll factor of the gather's outermost tap loop: full unrolling lets the
-// compiler hoist every row read of a point and spill.
-#ifndef NUFFTCT_GATHER_UNROLL
-#define NUFFTCT_GATHER_UNROLL 1
-#endif
-#define NUFFTCT_PRAGMA_(x) _Pragma(#x)
-#define NUFFTCT_UNROLL_(n) NUFFTCT_PRAGMA_(unroll n)
-
 template <typename T, int J, bool CW>
 __device__ __forceinline__ cx<T> wmac(cx<T> acc, cx<T> v, T wr, T wi) {
   if constexpr (CW) return cadd(acc, cmul(v, cx<T>{wr, wi}));
@@ -258,7 +240,9 @@ __device__ __forceinline__ cx<T> gather(const cx<T>* tile, const cx<T>* __restri
                                         const T (&w0r)[J], const T (&w0i)[J], const T (&w1r)[J],
                                         const T (&w1i)[J], const T (&w2r)[J], const T (&w2i)[J]) {
   cx<T> acc = {0, 0};
-  NUFFTCT_UNROLL_(NUFFTCT_GATHER_UNROLL)
+  // the outermost tap loop stays rolled: full unrolling lets the compiler
+  // hoist every row read of a point and spill
+#pragma unroll 1
   for (int a = 0; a < J; ++a) {
     cx<T> acc_a = {0, 0};
 #pragma unroll
@@ -314,13 +298,14 @@ __host__ __device__ inline int part_offset(int q0, int q1, int q2, int tile, int
 
 // ---------------------------------------------------------------------------
 template <typename T, int J, int TILE, bool CW, int DEG>
-__global__ __launch_bounds__(NT_INTERP)
-__attribute__((amdgpu_waves_per_eu(NUFFTCT_INTERP_WAVES_PER_EU))) void k_interp(const cx<T>* __restrict__ grid,
+__global__ __launch_bounds__(GridCfg<T>::NT_INTERP)
+__attribute__((amdgpu_waves_per_eu(GridCfg<T>::INTERP_WAVES))) void k_interp(const cx<T>* __restrict__ grid,
                                                cx<T>* __restrict__ out,
                                                const int32_t* __restrict__ perm,
                                                const TileTask* __restrict__ tasks,
                                                XcdSplit xs, PointGeom g,
                                                int nb, WeightPoly<T, DEG> P) {
+  constexpr int NT_INTERP = GridCfg<T>::NT_INTERP;
   constexpr int S = TILE + J - 1;
   constexpr int S2 = interp_pitch<T>(S);
   __shared__ float4 tile_mem[(S * S * S2 * (int)sizeof(cx<T>) + 15) / 16];
@@ -334,7 +319,7 @@ __attribute__((amdgpu_waves_per_eu(NUFFTCT_INTERP_WAVES_PER_EU))) void k_interp(
   {
     // CH loads per thread in flight before their LDS writes (a loop that
     // writes each cell as it arrives waits on every load in turn)
-    constexpr int NE = S * S * S, CH = NUFFTCT_INTERP_STAGE_CH;
+    constexpr int NE = S * S * S, CH = 8;
 #pragma unroll 1
     for (int i = threadIdx.x; i < NE; i += CH * NT_INTERP) {
       cx<T> v[CH];
@@ -358,23 +343,23 @@ __attribute__((amdgpu_waves_per_eu(NUFFTCT_INTERP_WAVES_PER_EU))) void k_interp(
     }
   }
   __syncthreads();
-#if NUFFTCT_INTERP_PREFETCH == 1
+  // the next point one iteration ahead: its whole geometry (FP64), or only its
+  // id (FP32, whose register budget has no room for the geometry)
   PtRaw nxt;
-  if ((int)threadIdx.x < tk.count) nxt = fetch_point(g, perm, tk.start + threadIdx.x);
-#elif NUFFTCT_INTERP_PREFETCH == 2
-  // only the next point id is fetched one iteration ahead (one register)
-  int pnxt = (int)threadIdx.x < tk.count ? perm[tk.start + threadIdx.x] : 0;
-#endif
+  int pnxt = 0;
+  if ((int)threadIdx.x < tk.count) {
+    if constexpr (GridCfg<T>::PREFETCH_GEOM) nxt = fetch_point(g, perm, tk.start + threadIdx.x);
+    else pnxt = perm[tk.start + threadIdx.x];
+  }
   for (int i = threadIdx.x; i < tk.count; i += NT_INTERP) {
-#if NUFFTCT_INTERP_PREFETCH == 1
-    const PtRaw cur = nxt;
-    if (i + NT_INTERP < tk.count) nxt = fetch_point(g, perm, tk.start + i + NT_INTERP);
-#elif NUFFTCT_INTERP_PREFETCH == 2
-    const PtRaw cur = point_of(g, pnxt);
-    if (i + NT_INTERP < tk.count) pnxt = perm[tk.start + i + NT_INTERP];
-#else
-    const PtRaw cur = fetch_point(g, perm, tk.start + i);
-#endif
+    PtRaw cur;
+    if constexpr (GridCfg<T>::PREFETCH_GEOM) {
+      cur = nxt;
+      if (i + NT_INTERP < tk.count) nxt = fetch_point(g, perm, tk.start + i + NT_INTERP);
+    } else {
+      cur = point_of(g, pnxt);
+      if (i + NT_INTERP < tk.count) pnxt = perm[tk.start + i + NT_INTERP];
+    }
     const int p = cur.p;
     int first[3];
     double frac[3];
@@ -495,8 +480,8 @@ __device__ __forceinline__ void spread_pair(unsigned long long* accp, double* ac
 //   FP64 form: FP64 atomic adds (ds_add_f64) on planar real / imaginary
 //     accumulators.
 template <typename T, int J, int TILE, bool CW, int DEG>
-__global__ __launch_bounds__(NT_SPREAD)
-__attribute__((amdgpu_waves_per_eu(NUFFTCT_SPREAD_WAVES_PER_EU))) void k_spread(const cx<T>* __restrict__ in,
+__global__ __launch_bounds__(GridCfg<T>::NT_SPREAD)
+__attribute__((amdgpu_waves_per_eu(GridCfg<T>::SPREAD_WAVES))) void k_spread(const cx<T>* __restrict__ in,
                                                       cx<T>* __restrict__ partials,
                                                       const int32_t* __restrict__ perm,
                                                       const TileTask* __restrict__ tasks,
@@ -504,6 +489,7 @@ __attribute__((amdgpu_waves_per_eu(NUFFTCT_SPREAD_WAVES_PER_EU))) void k_spread(
                                                       const float* __restrict__ bound,
                                                       XcdSplit xs, PointGeom g, int nb,
                                                       WeightPoly<T, DEG> P) {
+  constexpr int NT_SPREAD = GridCfg<T>::NT_SPREAD;
   constexpr bool FIXED = sizeof(T) == 4;
   constexpr int S = TILE + J - 1;
   constexpr int SS = S * S * S;
@@ -643,7 +629,7 @@ __attribute__((amdgpu_waves_per_eu(NUFFTCT_SPREAD_WAVES_PER_EU))) void k_spread(
     const int d0 = (delta >> 2) & 1, d1 = (delta >> 1) & 1, d2 = delta & 1;
     const int e1 = part_ext(d1, TILE, R), e2 = part_ext(d2, TILE, R);
     const int n = part_size(delta, TILE, R), base = part_base(delta, TILE, R);
-    if constexpr (FIXED && NUFFTCT_SPREAD_WRITE_PAIRS) {
+    if constexpr (FIXED) {
       // blocks whose rows have an even length (and an even base): two cells
       // of a row per lane, one 16-byte store
       if ((e2 & 1) == 0) {
@@ -681,7 +667,7 @@ __attribute__((amdgpu_waves_per_eu(NUFFTCT_SPREAD_WAVES_PER_EU))) void k_spread(
 // evaluates), accumulated exactly in 2^-32 units with every term rounded up,
 // then rounded up to float.
 template <typename T, int J, int TILE, bool CW, int DEG>
-__global__ __launch_bounds__(NT_SPREAD) void k_spread_bound(float* __restrict__ bound,
+__global__ __launch_bounds__(NT_BOUND) void k_spread_bound(float* __restrict__ bound,
                                                             const int32_t* __restrict__ perm,
                                                             const TileTask* __restrict__ tasks,
                                                             XcdSplit xs, PointGeom g, int nb,
@@ -695,10 +681,10 @@ __global__ __launch_bounds__(NT_SPREAD) void k_spread_bound(float* __restrict__ 
   const TileTask tk = tasks[task_id];
   const int b2 = tk.bin % nb, b1 = (tk.bin / nb) % nb, b0 = tk.bin / (nb * nb);
   const int o0 = b0 * TILE, o1 = b1 * TILE, o2 = b2 * TILE;
-  for (int idx = threadIdx.x; idx < SS; idx += NT_SPREAD) acc[idx] = 0ull;
+  for (int idx = threadIdx.x; idx < SS; idx += NT_BOUND) acc[idx] = 0ull;
   if (threadIdx.x == 0) s_max = 0ull;
   __syncthreads();
-  for (int i = threadIdx.x; i < tk.count; i += NT_SPREAD) {
+  for (int i = threadIdx.x; i < tk.count; i += NT_BOUND) {
     const PtRaw cur = fetch_point(g, perm, tk.start + i);
     int first[3];
     double frac[3];
@@ -729,7 +715,7 @@ __global__ __launch_bounds__(NT_SPREAD) void k_spread_bound(float* __restrict__ 
   }
   __syncthreads();
   unsigned long long m = 0ull;
-  for (int idx = threadIdx.x; idx < SS; idx += NT_SPREAD) m = acc[idx] > m ? acc[idx] : m;
+  for (int idx = threadIdx.x; idx < SS; idx += NT_BOUND) m = acc[idx] > m ? acc[idx] : m;
   __hip_atomic_fetch_max(&s_max, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -745,25 +731,12 @@ __global__ __launch_bounds__(NT_SPREAD) void k_spread_bound(float* __restrict__ 
 // ranges are read once per workgroup into LDS, then every cell issues its
 // (mostly single) partial loads independently.  With the block layout of the
 // partials, the cells of a row read consecutive words of each block.
-#ifndef NUFFTCT_MERGE_PAIRS
-#define NUFFTCT_MERGE_PAIRS 1
-#endif
-#ifndef NUFFTCT_MERGE_CELLS
-#define NUFFTCT_MERGE_CELLS 2
-#endif
-#ifndef NUFFTCT_MERGE_MASKED
-#define NUFFTCT_MERGE_MASKED 1
-#endif
-#ifndef NUFFTCT_MERGE_NT
-#define NUFFTCT_MERGE_NT 1024
-#endif
 template <typename T, int TILE>
-__global__ __launch_bounds__(TILE * TILE * TILE < NUFFTCT_MERGE_NT ? TILE * TILE * TILE
-                                                                    : NUFFTCT_MERGE_NT) void k_merge(
+__global__ __launch_bounds__(TILE * TILE * TILE < 1024 ? TILE * TILE * TILE : 1024) void k_merge(
     const cx<T>* __restrict__ partials, const int32_t* __restrict__ bin_tasks,
     const int32_t* __restrict__ order, cx<T>* __restrict__ grid, int nb, int K, int R, double r2) {
   constexpr int TT = TILE * TILE * TILE;
-  constexpr int NTM = TT < NUFFTCT_MERGE_NT ? TT : NUFFTCT_MERGE_NT;
+  constexpr int NTM = TT < 1024 ? TT : 1024;
   constexpr int PER = TT / NTM;
   const int64_t PS = part_stride(TILE, R);
   const int tile = order[blockIdx.x];
@@ -811,12 +784,8 @@ __global__ __launch_bounds__(TILE * TILE * TILE < NUFFTCT_MERGE_NT ? TILE * TILE
     cx<T> first[8];
 #pragma unroll
     for (int delta = 0; delta < 8; ++delta) {
-#if NUFFTCT_MERGE_MASKED
       first[delta] = cx<T>{0, 0};
       if (hit[delta]) first[delta] = partials[rng[2 * delta] * PS + off[delta]];
-#else
-      first[delta] = partials[hit[delta] ? rng[2 * delta] * PS + off[delta] : 0];
-#endif
     }
 #pragma unroll
     for (int delta = 0; delta < 8; ++delta)
@@ -960,14 +929,14 @@ hipError_t launch_one(const nufftct_plan& p, const void* src, void* dst, hipStre
     const dim3 grd((unsigned)((int64_t)p.xsplit.max_len * NUFFTCT_NUM_XCD));
     const PointGeom g = p.geom();
     if constexpr (OP == OP_SPREAD) {
-      hipLaunchKernelGGL((k_spread<T, J, TILE, CW, DEG>), grd, dim3(NT_SPREAD), 0, st,
+      hipLaunchKernelGGL((k_spread<T, J, TILE, CW, DEG>), grd, dim3(GridCfg<T>::NT_SPREAD), 0, st,
                          (const cx<T>*)src, (cx<T>*)p.d_partials, p.d_perm_s, p.d_tasks,
                          p.d_spread_order, p.d_bound, p.xsplit, g, p.nb, P);
     } else if constexpr (OP == OP_BOUND) {
-      hipLaunchKernelGGL((k_spread_bound<T, J, TILE, CW, DEG>), grd, dim3(NT_SPREAD), 0, st,
+      hipLaunchKernelGGL((k_spread_bound<T, J, TILE, CW, DEG>), grd, dim3(NT_BOUND), 0, st,
                          p.d_bound, p.d_perm_s, p.d_tasks, p.xsplit, g, p.nb, P);
     } else {
-      hipLaunchKernelGGL((k_interp<T, J, TILE, CW, DEG>), grd, dim3(NT_INTERP), 0, st,
+      hipLaunchKernelGGL((k_interp<T, J, TILE, CW, DEG>), grd, dim3(GridCfg<T>::NT_INTERP), 0, st,
                          (const cx<T>*)src, (cx<T>*)dst, p.d_perm, p.d_tasks, p.xsplit, g,
                          p.nb, P);
     }
@@ -1010,19 +979,17 @@ hipError_t merge(const nufftct_plan& p, void* grid, hipStream_t st, bool prune) 
   const int R = p.J - 1;
   const double r2 = prune ? p.ball_r2 : 1e300;
   const dim3 grd((unsigned)((int64_t)p.nb * p.nb * p.nb));
-#if NUFFTCT_MERGE_PAIRS
   if (p.tile == 16 && sizeof(T) == 4) {
-    hipLaunchKernelGGL((k_merge_pairs<16, NUFFTCT_MERGE_CELLS>), grd, dim3(1024), 0, st,
+    hipLaunchKernelGGL((k_merge_pairs<16, 2>), grd, dim3(1024), 0, st,
                        (const cx<float>*)p.d_partials,
                        p.d_bin_tasks, p.d_merge_order, (cx<float>*)grid, p.nb, (int)p.K, R, r2);
     return hipGetLastError();
   }
-#endif
   if (p.tile == 16)
-    hipLaunchKernelGGL((k_merge<T, 16>), grd, dim3(4096 < NUFFTCT_MERGE_NT ? 4096 : NUFFTCT_MERGE_NT), 0, st, (const cx<T>*)p.d_partials,
+    hipLaunchKernelGGL((k_merge<T, 16>), grd, dim3(1024), 0, st, (const cx<T>*)p.d_partials,
                        p.d_bin_tasks, p.d_merge_order, (cx<T>*)grid, p.nb, (int)p.K, R, r2);
   else if (p.tile == 8)
-    hipLaunchKernelGGL((k_merge<T, 8>), grd, dim3(512 < NUFFTCT_MERGE_NT ? 512 : NUFFTCT_MERGE_NT), 0, st, (const cx<T>*)p.d_partials,
+    hipLaunchKernelGGL((k_merge<T, 8>), grd, dim3(512), 0, st, (const cx<T>*)p.d_partials,
                        p.d_bin_tasks, p.d_merge_order, (cx<T>*)grid, p.nb, (int)p.K, R, r2);
   else
     return hipErrorInvalidValue;

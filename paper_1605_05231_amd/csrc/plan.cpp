@@ -100,10 +100,6 @@ static void point_omega(const nufftct_plan& p, const std::vector<double>& geom, 
 }
 #pragma clang fp contract(on)
 
-#ifndef NUFFTCT_SPREAD_LPT
-#define NUFFTCT_SPREAD_LPT 1
-#endif
-
 struct Binning {
   std::vector<int32_t> perm;    // interpolation order
   std::vector<int32_t> perm_s;  // spreading order (same tasks)
@@ -598,7 +594,6 @@ static int create(nufftct_plan** out, int64_t N, int64_t K, int J, int kernel, d
                        [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
       if ((rc = upload((void**)&p->d_merge_order, order.data(), order.size(), st))) return bail(rc);
     }
-#if NUFFTCT_SPREAD_LPT
     {
       // spreading dispatch order: inside each XCD's task range the largest
       // tasks first, so that the last ones to start are short
@@ -609,7 +604,6 @@ static int create(nufftct_plan** out, int64_t N, int64_t K, int J, int kernel, d
                          [&](int32_t a, int32_t b) { return B.tasks[a].count > B.tasks[b].count; });
       if ((rc = upload((void**)&p->d_spread_order, torder.data(), torder.size(), st))) return bail(rc);
     }
-#endif
     const size_t cxb = precision == NUFFTCT_FP32 ? 8 : 16;
     // per-task stride: the halo's S^3 cells rounded up to 16 (the merge's
     // loads then start on 128-byte lines)

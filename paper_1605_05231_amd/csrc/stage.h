@@ -4,10 +4,6 @@
 
 #include "cx.h"
 
-#ifndef NUFFTCT_BATCH_LOADS
-#define NUFFTCT_BATCH_LOADS 1
-#endif
-
 namespace stage {
 
 // Staging of a tile of NE elements by NTH threads: thread t handles elements
@@ -18,7 +14,6 @@ namespace stage {
 // registers that hold them.
 template <typename T, int NE, int NTH, int CH = (NE + NTH - 1) / NTH, typename Ld, typename St>
 __device__ __forceinline__ void tile(int tid, Ld&& ld, St&& st) {
-#if NUFFTCT_BATCH_LOADS
   constexpr int PER = (NE + NTH - 1) / NTH;
 #pragma unroll
   for (int k0 = 0; k0 < PER; k0 += CH) {
@@ -34,9 +29,6 @@ __device__ __forceinline__ void tile(int tid, Ld&& ld, St&& st) {
       if (k0 + k < PER && (NE % NTH == 0 || idx < NE)) st(idx, v[k]);
     }
   }
-#else
-  for (int idx = tid; idx < NE; idx += NTH) st(idx, ld(idx));
-#endif
 }
 
 }  // namespace stage
