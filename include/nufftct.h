@@ -127,7 +127,8 @@ int nufftct_plan_create_radial(nufftct_plan** out, int64_t N, int64_t K, int J, 
  * plans (tile edge 16 or 8 cells x 1024..16384 points per task), times one
  * forward + adjoint (flags as for nufftct_forward) of each on `stream`, and
  * records the fastest in a process-wide table that every later plan creation
- * with the same (N, K, J, kernel, precision, n_lines, n_r) uses.  With the
+ * with the same (N, K, J, kernel, precision, n_lines, n_r) and the same
+ * direction coordinates (compared by a hash of their bytes) uses.  With the
  * environment variable NUFFTCT_TUNE_CACHE naming a file, results are appended
  * there and read back by later processes.  NUFFTCT_TILE / NUFFTCT_MAXPTS in the
  * environment override the table.  Blocking; allocates temporary buffers.
@@ -200,6 +201,14 @@ int nufftct_plan_destroy(nufftct_plan* plan);
 /* Plan introspection: sizes of the plan (any pointer may be NULL). */
 int nufftct_plan_info(const nufftct_plan* plan, int64_t* N, int64_t* K, int* J,
                       int64_t* M, int64_t* n_r, int* precision, int64_t* workspace_bytes);
+
+/*
+ * The plan's tiling of the grid for interpolation and spreading: the tile
+ * edge in grid cells and the largest number of points per task (from the
+ * autotuner's table, the environment, or the defaults; see
+ * nufftct_autotune_radial).  Either pointer may be NULL.
+ */
+int nufftct_plan_tiling(const nufftct_plan* plan, int* tile, int* max_pts);
 
 /* timing slot of the kernel that merges the spread's per-task halo tiles into the grid */
 #define NUFFTCT_TIMING_MERGE 6

@@ -5,7 +5,7 @@ TEST INFRASTRUCTURE (oracle).  FP64.
 Follows the factorisation of Section 2.1.3, eq 2.11, x~ = T_sparse F P x:
   1. P: multiply the volume by the separable scaling s(m0) s(m1) s(m2) and
      zero-pad it onto the K^3 grid, voxel m stored at index (m mod K);
-  2. F: unnormalised 3D FFT of the padded grid (numpy.fft.fftn), so that
+  2. F: unnormalised 3D FFT of the padded grid (a library FFT), so that
      Y[kappa mod K] = sum_m s(m) x[m] exp(-i gamma kappa . m);
   3. T_sparse: for every point, the J^3 tensor-product taps of the neighbour
      rule, X(omega) ~= sum_{a,b,c} w0_a w1_b w2_c Y[(kappa0_a, kappa1_b, kappa2_c) mod K].
@@ -18,8 +18,13 @@ No blocking or reordering beyond processing the points in chunks.
 from __future__ import annotations
 
 import numpy as np
+from scipy import fft as sfft
 
 from . import kernels
+
+# Threads of the library FFT (scipy.fft's pocketfft); the CPU baseline sets it
+# to the host's core count.  The transform is the same for any value.
+FFT_WORKERS = 1
 
 
 class Params:
@@ -58,7 +63,7 @@ def prescale_pad(x: np.ndarray, prm: Params) -> np.ndarray:
 
 def oversampled_spectrum(x: np.ndarray, prm: Params) -> np.ndarray:
     """Steps 1-2: Y = FFT_K(P x), numpy layout (frequency kappa at index kappa mod K)."""
-    return np.fft.fftn(prescale_pad(np.asarray(x, dtype=np.complex128), prm))
+    return sfft.fftn(prescale_pad(np.asarray(x, dtype=np.complex128), prm), workers=FFT_WORKERS)
 
 
 def interpolate(Y: np.ndarray, omega: np.ndarray, prm: Params, chunk: int = 1 << 16) -> np.ndarray:
@@ -120,7 +125,7 @@ def forward(x: np.ndarray, omega: np.ndarray, prm: Params) -> np.ndarray:
 
 def inverse_spectrum(Yt: np.ndarray, prm: Params) -> np.ndarray:
     """Unnormalised inverse FFT: y~[q] = sum_k Y~[k] exp(+2 pi i k.q/K)."""
-    return np.fft.ifftn(Yt) * float(prm.K) ** 3
+    return sfft.ifftn(Yt, workers=FFT_WORKERS) * float(prm.K) ** 3
 
 
 def adjoint(g: np.ndarray, omega: np.ndarray, prm: Params) -> np.ndarray:

@@ -123,6 +123,12 @@ class Plan:
         keys = ["N", "K", "J", "M", "n_r", "precision", "workspace_bytes"]
         return {k: v.value for k, v in zip(keys, vals)}
 
+    def tiling(self) -> tuple:
+        """(tile edge, points per task) of the plan's interpolation/spreading tasks."""
+        t, m = C.c_int(), C.c_int()
+        _lib.check(_lib.load().nufftct_plan_tiling(self._ptr, C.byref(t), C.byref(m)))
+        return (t.value, m.value)
+
     # -- operators ----------------------------------------------------------
     @staticmethod
     def _flags(radial: bool, deriv: bool) -> int:

@@ -43,6 +43,7 @@ SIGNATURES = {
     "nufftct_plan_info": (C.c_int, [_p, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(C.c_int),
                                     C.POINTER(_i64), C.POINTER(_i64), C.POINTER(C.c_int),
                                     C.POINTER(_i64)]),
+    "nufftct_plan_tiling": (C.c_int, [_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "nufftct_set_timing": (C.c_int, [_p, C.c_int]),
     "nufftct_get_stage_times": (C.c_int, [_p, _dp, C.POINTER(_i64), C.c_int]),
     "nufftct_batch_create": (C.c_int, [C.POINTER(_p), C.c_int, C.POINTER(_i64), C.POINTER(_i64),

@@ -467,50 +467,106 @@ __device__ __forceinline__ void spread_pair(unsigned long long* accp, double* ac
 //
 // LDS accumulation (f32 LDS atomic adds run ~8x slower than 64-bit ones on
 // gfx950):
-//   FP32 path: exact integer sums, both components in one 64-bit word.  With
-//     the task's scale s = 2^30 / (vmax B) (2^29 for complex weights), vmax
-//     the largest component of the task's inputs and B the plan-time bound on
-//     sum_points prod_axes |w| at any cell of the halo (k_spread_bound), every
-//     cell's sums of rounded contributions q = floor(s u + 1/2) stay inside
-//     [-2^31, 2^31).  Each tap adds the word q_re 2^32 + q_im (two's
-//     complement) with one ds_add_u64; the low half of a sum is then the sum
-//     of q_im and the rest the sum of q_re, the carries between them being
-//     exact.  The per-contribution error is <= 0.5 / s, and the sum does not
-//     depend on the order of the atomics (bitwise reproducible).
+//   FP32 path: exact integer sums, both components in one 64-bit word.  A
+//     value v of magnitude a = max(|re v|, |im v|) is scaled to
+//     s v = 2^-c f v with f = 2^30 / (u B) (2^29 for complex weights), where
+//     u 2^c bounds the magnitudes of its class (below) and B is the plan-time
+//     bound on sum_points prod_axes |w| at any cell of the halo
+//     (k_spread_bound); every cell's sums of rounded contributions
+//     q = floor(s u + 1/2) then stay inside [-2^31, 2^31).  Each tap adds the
+//     word q_re 2^32 + q_im (two's complement) with one ds_add_u64; the low
+//     half of a sum is the sum of q_im and the rest the sum of q_re, the
+//     carries between them being exact.  The per-contribution error is
+//     <= 0.5 / s, and the sum does not depend on the order of the atomics
+//     (bitwise reproducible).  The scaling by 2^-c is exact (ldexp) and the
+//     decoding runs in FP64, so tiny and huge magnitudes keep their precision.
+//   Magnitude classes: the error bound follows the largest magnitude that
+//     shares the scale, so a task whose non-zero magnitudes span more than
+//     2^CLASS_BITS is spread in several passes, one per class of binades
+//     (each class holds the occupied binades within CLASS_BITS of its top),
+//     each with its own scale; later passes add their decoded sums to the
+//     partial.  A value's contributions are then accurate to
+//     <= 2^(CLASS_BITS - 30) B times its own magnitude (one pass, and the
+//     task maximum itself as the bound, in the usual case).
+//   Non-finite values: they take no part in the integer sums; the cells of
+//     their J^3 footprints are flagged and written as NaN.
 //   FP64 form: FP64 atomic adds (ds_add_f64) on planar real / imaginary
 //     accumulators.
-template <typename T, int J, int TILE, bool CW, int DEG>
-__global__ __launch_bounds__(GridCfg<T>::NT_SPREAD)
-__attribute__((amdgpu_waves_per_eu(GridCfg<T>::SPREAD_WAVES))) void k_spread(const cx<T>* __restrict__ in,
-                                                      cx<T>* __restrict__ partials,
-                                                      const int32_t* __restrict__ perm,
-                                                      const TileTask* __restrict__ tasks,
-                                                      const int32_t* __restrict__ torder,
-                                                      const float* __restrict__ bound,
-                                                      XcdSplit xs, PointGeom g, int nb,
-                                                      WeightPoly<T, DEG> P) {
+constexpr int CLASS_BITS = 12;
+constexpr int MAX_CLASSES = 32;  // finite non-zero floats span 277 binades
+constexpr int EXP_OFF = 148;     // frexp exponents of finite floats: [-148, 128]
+constexpr int EXP_WORDS = 9;     // occupancy bits of those 277 exponents
+
+// binary exponent e of a > 0 (a in [2^(e-1), 2^e)), denormals included
+__device__ __forceinline__ int exp_of(float a) { return __builtin_amdgcn_frexp_expf(a); }
+
+template <int J, int S>
+__device__ __forceinline__ void flag_footprint(unsigned* flags, int base) {
+  for (int a = 0; a < J; ++a)
+    for (int b = 0; b < J; ++b)
+      for (int c = 0; c < J; ++c) {
+        const int cell = base + (a * S + b) * S + c;
+        atomicOr(&flags[cell >> 5], 1u << (cell & 31));
+      }
+}
+
+// The spreading of one task.  REST = false: the task's first class (its only
+// one in the usual case), the non-finite flags, and the number of classes in
+// ncls[task] (1, or 2 when more classes follow).  REST = true: the further
+// classes of the tasks that have them (others return at once), added to the
+// partial.  The two are separate kernels so that the rare multi-pass loop does
+// not cost the usual single pass any registers.
+template <typename T, int J, int TILE, bool CW, int DEG, bool REST>
+__device__ __forceinline__ void spread_task(const cx<T>* __restrict__ in,
+                                            cx<T>* __restrict__ partials,
+                                            const int32_t* __restrict__ perm,
+                                            const TileTask* __restrict__ tasks,
+                                            const int32_t* __restrict__ torder,
+                                            const float* __restrict__ bound,
+                                            int32_t* __restrict__ ncls_of, const XcdSplit& xs,
+                                            const PointGeom& g, int nb,
+                                            const WeightPoly<T, DEG>& P) {
   constexpr int NT_SPREAD = GridCfg<T>::NT_SPREAD;
   constexpr bool FIXED = sizeof(T) == 4;
   constexpr int S = TILE + J - 1;
   constexpr int SS = S * S * S;
+  constexpr int R = J - 1;
+  constexpr float FMAX = 3.402823466e38f;
   // FP32: one packed 64-bit word per cell.  FP64: planar accumulators (all
   // real parts, then all imaginary parts), so that a wave's 64-bit atomics
   // spread over every LDS bank instead of half of them.
   __shared__ double acc[FIXED ? SS : 2 * SS];
-  __shared__ unsigned int s_maxbits;
+  __shared__ unsigned s_nan[FIXED && !REST ? (SS + 31) / 32 : 1];
+  __shared__ unsigned s_occ[EXP_WORDS];
+  __shared__ int s_ctop[MAX_CLASSES];
+  __shared__ unsigned s_maxbits;
+  __shared__ int s_emin, s_bad, s_ncls;
   unsigned long long* accp = reinterpret_cast<unsigned long long*>(acc);
   int64_t task_id = xcd_task(blockIdx.x, xs);
   if (task_id < 0) return;
   if (torder) task_id = torder[task_id];  // largest tasks of each XCD range first
+  if (REST && ncls_of[task_id] <= 1) return;
   const TileTask tk = tasks[task_id];
   const int b2 = tk.bin % nb, b1 = (tk.bin / nb) % nb, b0 = tk.bin / (nb * nb);
   const int o0 = b0 * TILE, o1 = b1 * TILE, o2 = b2 * TILE;
   for (int idx = threadIdx.x; idx < (FIXED ? SS : 2 * SS); idx += NT_SPREAD) acc[idx] = 0.0;
-  T scale = (T)1;
+  // magnitude statistics of the task's values (FP32)
+  float vmax = 0.f;
+  int emax = 0, ncls = 1;
+  bool bad = false, multi = false;
   if constexpr (FIXED) {
-    if (threadIdx.x == 0) s_maxbits = 0u;
+    if constexpr (!REST)
+      for (int idx = threadIdx.x; idx < (SS + 31) / 32; idx += NT_SPREAD) s_nan[idx] = 0u;
+    if (threadIdx.x == 0) {
+      s_maxbits = 0u;
+      s_emin = 1 << 20;
+      s_bad = 0;
+    }
+    if (threadIdx.x < EXP_WORDS) s_occ[threadIdx.x] = 0u;
     __syncthreads();
     float m = 0.f;
+    int emin = 1 << 20;
+    bool nf = false;
     // four points per step, so that four dependent load pairs are in flight
     for (int i0 = threadIdx.x; i0 < tk.count; i0 += 4 * NT_SPREAD) {
       int id[4];
@@ -523,15 +579,54 @@ __attribute__((amdgpu_waves_per_eu(GridCfg<T>::SPREAD_WAVES))) void k_spread(con
       for (int k = 0; k < 4; ++k)
         if (id[k] >= 0) {
           const cx<T> v = in[id[k]];
-          m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+          const float ax = fabsf(v.x), ay = fabsf(v.y);
+          if (!(ax <= FMAX) || !(ay <= FMAX)) {
+            nf = true;  // NaN or infinite component
+          } else {
+            const float a = fmaxf(ax, ay);
+            if (a > 0.f) {
+              m = fmaxf(m, a);
+              emin = min(emin, exp_of(a));
+            }
+          }
         }
     }
     // non-negative floats order like their bit patterns
     atomicMax(&s_maxbits, __float_as_uint(m));
+    atomicMin(&s_emin, emin);
+    if (nf) s_bad = 1;
     __syncthreads();
-    const float vmax = __uint_as_float(s_maxbits);
-    const float vb = vmax * bound[task_id];
-    scale = vb > 0.f ? (CW ? 536870912.0f : 1073741824.0f) / vb : 1.0f;  // 2^29 or 2^30
+    vmax = __uint_as_float(s_maxbits);
+    bad = s_bad != 0;
+    emax = vmax > 0.f ? exp_of(vmax) : 0;
+    multi = vmax > 0.f && emax - s_emin >= CLASS_BITS;
+    if constexpr (!REST) {
+      if (threadIdx.x == 0) ncls_of[task_id] = multi ? 2 : 1;
+    } else {
+      // the occupied binades, then the classes: each starts at the highest
+      // occupied binade below the previous class and spans CLASS_BITS of them
+      for (int i0 = threadIdx.x; i0 < tk.count; i0 += NT_SPREAD) {
+        const cx<T> v = in[perm[tk.start + i0]];
+        const float a = fmaxf(fabsf(v.x), fabsf(v.y));
+        if (a > 0.f && a <= FMAX) {
+          const int e = exp_of(a) + EXP_OFF;
+          atomicOr(&s_occ[e >> 5], 1u << (e & 31));
+        }
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int n = 0, e = emax;
+        const int lo = s_emin;
+        while (e >= lo && n < MAX_CLASSES) {
+          s_ctop[n++] = e;
+          e -= CLASS_BITS;
+          while (e >= lo && !((s_occ[(e + EXP_OFF) >> 5] >> ((e + EXP_OFF) & 31)) & 1u)) --e;
+        }
+        s_ncls = n;
+      }
+      __syncthreads();
+      ncls = s_ncls;
+    }
   } else {
     __syncthreads();
   }
@@ -542,69 +637,116 @@ __attribute__((amdgpu_waves_per_eu(GridCfg<T>::SPREAD_WAVES))) void k_spread(con
   // budget it would exceed) the points of a unit are spread one by one
   constexpr bool PAIRED = !CW && sizeof(T) == 4;
   const int np = tk.npairs, nunits = tk.count - np;
-  PtRaw nxt, nxt2;
-  cx<T> vnxt = {0, 0}, vnxt2 = {0, 0};
-  auto fetch_unit = [&](int u) {  // one unit ahead (its second point if paired)
-    const int e = u < np ? 2 * u : np + u;
-    nxt = fetch_point(g, perm, tk.start + e);
-    vnxt = in[nxt.p];
-    vnxt2 = cx<T>{0, 0};
-    if (PAIRED && u < np) {
-      nxt2 = fetch_point(g, perm, tk.start + e + 1);
-      vnxt2 = in[nxt2.p];
+  cx<T>* dst = partials + task_id * (int64_t)part_stride(TILE, R);
+  // no accumulation is needed when every value is zero or non-finite
+  const bool work = !FIXED || vmax > 0.f;
+  for (int cls = REST ? 1 : 0; cls < (REST ? ncls : 1); ++cls) {
+    // the class's scale: v -> ldexp(v, -ctop) f
+    const int ctop = REST ? s_ctop[cls] : emax;
+    float f = 1.f;
+    double inv = 1.0;
+    if constexpr (FIXED) {
+      if (REST && cls > 1) {
+        __syncthreads();  // the previous pass's write-out has read the accumulators
+        for (int idx = threadIdx.x; idx < SS; idx += NT_SPREAD) acc[idx] = 0.0;
+        __syncthreads();
+      }
+      const double u = cls == 0 ? (double)ldexpf(vmax, -emax) : 1.0;  // class bound / 2^ctop
+      const double bnd = (double)bound[task_id];
+      if (vmax > 0.f && bnd > 0.0) {
+        f = (float)((CW ? 536870912.0 : 1073741824.0) / (u * bnd));  // 2^29 or 2^30
+        inv = ldexp(1.0 / (double)f, ctop);
+      }
     }
-  };
-  if ((int)threadIdx.x < nunits) fetch_unit(threadIdx.x);
-  for (int u = threadIdx.x; u < nunits; u += NT_SPREAD) {
-    PtRaw cur = nxt, cur2 = nxt2;
-    cx<T> v = vnxt, v2 = vnxt2;
-    const bool pair = u < np;
-    if (u + NT_SPREAD < nunits) fetch_unit(u + NT_SPREAD);
-    if (!PAIRED && pair) {
-      cur2 = fetch_point(g, perm, tk.start + 2 * u + 1);
-      v2 = in[cur2.p];
-    }
-    v = cx<T>{v.x * scale, v.y * scale};
-    v2 = cx<T>{v2.x * scale, v2.y * scale};
-    int first[3], first2[3] = {0, 0, 0};
-    double frac[3], frac2[3] = {0.0, 0.0, 0.0};
-    point_taps<sizeof(T) == 4>(g, cur, J, first, frac);
-    const int l0 = first[0] - o0, l1 = first[1] - o1, l2 = first[2] - o2;
-    // the host bins with the same FP64 arithmetic, so every point of the task
-    // lies in its tile; the check only keeps LDS accesses in bounds
-    const bool in1 = (unsigned)l0 < (unsigned)TILE && (unsigned)l1 < (unsigned)TILE &&
-                     (unsigned)l2 < (unsigned)TILE;
-    T w0r[J], w0i[J], w1r[J], w1i[J], w2r[J], w2i[J];
-    axis_weights<T, J, DEG, CW>(P, frac[0], w0r, w0i);
-    axis_weights<T, J, DEG, CW>(P, frac[1], w1r, w1i);
-    axis_weights<T, J, DEG, CW>(P, frac[2], w2r, w2i);
-    bool same = true;  // the second point shares the first tap cell
-    if (pair) {
-      point_taps<sizeof(T) == 4>(g, cur2, J, first2, frac2);
-      same = first2[0] == first[0] && first2[1] == first[1] && first2[2] == first[2];
-    }
-    if constexpr (PAIRED) {
-      // (a single point, or a pair whose first cells differ, adds a zero here)
-      T x0r[J], x0i[J], x1r[J], x1i[J], x2r[J], x2i[J];
-      const bool both = pair && same;
-      axis_weights<T, J, DEG, CW>(P, both ? frac2[0] : frac[0], x0r, x0i);
-      axis_weights<T, J, DEG, CW>(P, both ? frac2[1] : frac[1], x1r, x1i);
-      axis_weights<T, J, DEG, CW>(P, both ? frac2[2] : frac[2], x2r, x2i);
-      const cx<T> vq = both ? v2 : cx<T>{0, 0};
-      if (in1)
-        spread_pair<T, J, S, SS>(accp, acc, v, vq, (l0 * S + l1) * S + l2, w0r, w1r, w2r, x0r,
-                                 x1r, x2r);
-    } else {
-      if (in1)
-        spread_one<T, J, S, SS, CW>(accp, acc, v, (l0 * S + l1) * S + l2, w0r, w0i, w1r, w1i,
-                                    w2r, w2i);
-    }
-    if (pair && (!PAIRED || !same)) {
-      // the second point on its own (or first cells that differ in the
-      // device's rounding of a tie)
+    const int clo = multi ? ctop - CLASS_BITS : -(1 << 20);
+    // the scaled value of the class, 0 for values of other classes or
+    // non-finite ones; FP64 values pass unchanged
+    auto prep = [&](cx<T> v) -> cx<T> {
+      if constexpr (FIXED) {
+        const float ax = fabsf(v.x), ay = fabsf(v.y);
+        if (bad && (!(ax <= FMAX) || !(ay <= FMAX))) return cx<T>{0, 0};
+        if (multi) {
+          const float a = fmaxf(ax, ay);
+          const int e = a > 0.f ? exp_of(a) : clo;
+          if (e > ctop || e <= clo) return cx<T>{0, 0};
+        }
+        return cx<T>{ldexpf(v.x, -ctop) * f, ldexpf(v.y, -ctop) * f};
+      } else {
+        return v;
+      }
+    };
+    auto nonfinite = [](cx<T> v) { return !(fabsf((float)v.x) <= FMAX) || !(fabsf((float)v.y) <= FMAX); };
+    PtRaw nxt, nxt2;
+    cx<T> vnxt = {0, 0}, vnxt2 = {0, 0};
+    auto fetch_unit = [&](int u) {  // one unit ahead (its second point if paired)
+      const int e = u < np ? 2 * u : np + u;
+      nxt = fetch_point(g, perm, tk.start + e);
+      vnxt = in[nxt.p];
+      vnxt2 = cx<T>{0, 0};
+      if (PAIRED && u < np) {
+        nxt2 = fetch_point(g, perm, tk.start + e + 1);
+        vnxt2 = in[nxt2.p];
+      }
+    };
+    if ((work || bad) && (int)threadIdx.x < nunits) fetch_unit(threadIdx.x);
+    for (int u = threadIdx.x; (work || bad) && u < nunits; u += NT_SPREAD) {
+      PtRaw cur = nxt, cur2 = nxt2;
+      cx<T> v = vnxt, v2 = vnxt2;
+      const bool pair = u < np;
+      if (u + NT_SPREAD < nunits) fetch_unit(u + NT_SPREAD);
+      if (!PAIRED && pair) {
+        cur2 = fetch_point(g, perm, tk.start + 2 * u + 1);
+        v2 = in[cur2.p];
+      }
+      const bool bad1 = FIXED && !REST && bad && nonfinite(v);
+      const bool bad2 = FIXED && !REST && bad && pair && nonfinite(v2);
+      v = prep(v);
+      v2 = prep(v2);
+      int first[3], first2[3] = {0, 0, 0};
+      double frac[3], frac2[3] = {0.0, 0.0, 0.0};
+      point_taps<sizeof(T) == 4>(g, cur, J, first, frac);
+      const int l0 = first[0] - o0, l1 = first[1] - o1, l2 = first[2] - o2;
+      // the host bins with the same FP64 arithmetic, so every point of the task
+      // lies in its tile; the check only keeps LDS accesses in bounds
+      const bool in1 = (unsigned)l0 < (unsigned)TILE && (unsigned)l1 < (unsigned)TILE &&
+                       (unsigned)l2 < (unsigned)TILE;
+      T w0r[J], w0i[J], w1r[J], w1i[J], w2r[J], w2i[J];
+      axis_weights<T, J, DEG, CW>(P, frac[0], w0r, w0i);
+      axis_weights<T, J, DEG, CW>(P, frac[1], w1r, w1i);
+      axis_weights<T, J, DEG, CW>(P, frac[2], w2r, w2i);
+      bool same = true;  // the second point shares the first tap cell
+      if (pair) {
+        point_taps<sizeof(T) == 4>(g, cur2, J, first2, frac2);
+        same = first2[0] == first[0] && first2[1] == first[1] && first2[2] == first[2];
+      }
       const int m0 = first2[0] - o0, m1 = first2[1] - o1, m2 = first2[2] - o2;
-      if ((unsigned)m0 < (unsigned)TILE && (unsigned)m1 < (unsigned)TILE &&
-          (unsigned)m2 < (unsigned)TILE) {
+      const bool in2 = pair && (unsigned)m0 < (unsigned)TILE && (unsigned)m1 < (unsigned)TILE &&
+                       (unsigned)m2 < (unsigned)TILE;
+      if constexpr (FIXED && !REST) {
+        if (bad1 && in1) flag_footprint<J, S>(s_nan, (l0 * S + l1) * S + l2);
+        if (bad2 && in2) flag_footprint<J, S>(s_nan, (m0 * S + m1) * S + m2);
+      }
+      const bool nz1 = v.x != (T)0 || v.y != (T)0, nz2 = pair && (v2.x != (T)0 || v2.y != (T)0);
+      if constexpr (PAIRED) {
+        // (a single point, or a pair whose first cells differ, adds a zero here)
+        const bool both = pair && same;
+        if (in1 && (nz1 || (both && nz2))) {
+          T x0r[J], x0i[J], x1r[J], x1i[J], x2r[J], x2i[J];
+          axis_weights<T, J, DEG, CW>(P, both ? frac2[0] : frac[0], x0r, x0i);
+          axis_weights<T, J, DEG, CW>(P, both ? frac2[1] : frac[1], x1r, x1i);
+          axis_weights<T, J, DEG, CW>(P, both ? frac2[2] : frac[2], x2r, x2i);
+          const cx<T> vq = both ? v2 : cx<T>{0, 0};
+          spread_pair<T, J, S, SS>(accp, acc, v, vq, (l0 * S + l1) * S + l2, w0r, w1r, w2r, x0r,
+                                   x1r, x2r);
+        }
+      } else {
+        if (in1 && nz1)
+          spread_one<T, J, S, SS, CW>(accp, acc, v, (l0 * S + l1) * S + l2, w0r, w0i, w1r, w1i,
+                                      w2r, w2i);
+      }
+      if (pair && (!PAIRED || !same) && in2 && nz2) {
+        // the second point on its own (or first cells that differ in the
+        // device's rounding of a tie)
         axis_weights<T, J, DEG, CW>(P, frac2[0], w0r, w0i);
         axis_weights<T, J, DEG, CW>(P, frac2[1], w1r, w1i);
         axis_weights<T, J, DEG, CW>(P, frac2[2], w2r, w2i);
@@ -612,54 +754,83 @@ __attribute__((amdgpu_waves_per_eu(GridCfg<T>::SPREAD_WAVES))) void k_spread(con
                                     w2r, w2i);
       }
     }
-  }
-  __syncthreads();
-  // write the partial block by block (consecutive threads, consecutive
-  // addresses), see part_offset
-  constexpr int R = J - 1;
-  cx<T>* dst = partials + task_id * (int64_t)part_stride(TILE, R);
-  const double inv = 1.0 / (double)scale;
-  auto decode = [&](unsigned long long w) {  // the two sums of a packed word
-    const long long lo = (long long)(int)(unsigned int)(w & 0xffffffffull);
-    const long long hi = (long long)(w - (unsigned long long)lo) >> 32;
-    return cx<T>{(T)((double)hi * inv), (T)((double)lo * inv)};
-  };
+    __syncthreads();
+    // write the partial block by block (consecutive threads, consecutive
+    // addresses), see part_offset; further classes add to what the first wrote
+    auto decode = [&](unsigned long long w, int cell) {  // the two sums of a packed word
+      const long long lo = (long long)(int)(unsigned int)(w & 0xffffffffull);
+      const long long hi = (long long)(w - (unsigned long long)lo) >> 32;
+      cx<T> r = cx<T>{(T)((double)hi * inv), (T)((double)lo * inv)};
+      if constexpr (!REST)
+        if (bad && ((s_nan[cell >> 5] >> (cell & 31)) & 1u)) r = cx<T>{(T)NAN, (T)NAN};
+      return r;
+    };
 #pragma unroll
-  for (int delta = 0; delta < 8; ++delta) {
-    const int d0 = (delta >> 2) & 1, d1 = (delta >> 1) & 1, d2 = delta & 1;
-    const int e1 = part_ext(d1, TILE, R), e2 = part_ext(d2, TILE, R);
-    const int n = part_size(delta, TILE, R), base = part_base(delta, TILE, R);
-    if constexpr (FIXED) {
-      // blocks whose rows have an even length (and an even base): two cells
-      // of a row per lane, one 16-byte store
-      if ((e2 & 1) == 0) {
-        constexpr int NTS2 = NT_SPREAD;
-#pragma unroll
-        for (int k = 0; k < (part_size(delta, TILE, R) / 2 + NTS2 - 1) / NTS2; ++k) {
-          const int j = (int)threadIdx.x + k * NTS2;
-          if (j < n / 2) {
-            const int idx = 2 * j;
-            const int r2 = idx % e2, r1 = (idx / e2) % e1, r0 = idx / (e1 * e2);
-            const int cell = ((r0 + d0 * TILE) * S + (r1 + d1 * TILE)) * S + (r2 + d2 * TILE);
-            const cx<T> a = decode(accp[cell]), b = decode(accp[cell + 1]);
-            reinterpret_cast<float4*>(dst + base)[j] = make_float4(a.x, a.y, b.x, b.y);
-          }
-        }
-        continue;
-      }
-    }
-    for (int idx = threadIdx.x; idx < n; idx += NT_SPREAD) {
-      const int r2 = idx % e2, r1 = (idx / e2) % e1, r0 = idx / (e1 * e2);
-      const int cell = ((r0 + d0 * TILE) * S + (r1 + d1 * TILE)) * S + (r2 + d2 * TILE);
-      cx<T> v;
+    for (int delta = 0; delta < 8; ++delta) {
+      const int d0 = (delta >> 2) & 1, d1 = (delta >> 1) & 1, d2 = delta & 1;
+      const int e1 = part_ext(d1, TILE, R), e2 = part_ext(d2, TILE, R);
+      const int n = part_size(delta, TILE, R), base = part_base(delta, TILE, R);
       if constexpr (FIXED) {
-        v = decode(accp[cell]);
-      } else {
-        v = cx<T>{(T)acc[cell], (T)acc[SS + cell]};
+        // blocks whose rows have an even length (and an even base): two cells
+        // of a row per lane, one 16-byte store
+        if ((e2 & 1) == 0) {
+          constexpr int NTS2 = NT_SPREAD;
+#pragma unroll
+          for (int k = 0; k < (part_size(delta, TILE, R) / 2 + NTS2 - 1) / NTS2; ++k) {
+            const int j = (int)threadIdx.x + k * NTS2;
+            if (j < n / 2) {
+              const int idx = 2 * j;
+              const int r2 = idx % e2, r1 = (idx / e2) % e1, r0 = idx / (e1 * e2);
+              const int cell = ((r0 + d0 * TILE) * S + (r1 + d1 * TILE)) * S + (r2 + d2 * TILE);
+              const cx<T> a = decode(accp[cell], cell), b = decode(accp[cell + 1], cell + 1);
+              float4 o = make_float4(a.x, a.y, b.x, b.y);
+              float4* q = reinterpret_cast<float4*>(dst + base) + j;
+              if constexpr (REST) {
+                const float4 p = *q;
+                o = make_float4(p.x + o.x, p.y + o.y, p.z + o.z, p.w + o.w);
+              }
+              *q = o;
+            }
+          }
+          continue;
+        }
       }
-      dst[base + idx] = v;
+      for (int idx = threadIdx.x; idx < n; idx += NT_SPREAD) {
+        const int r2 = idx % e2, r1 = (idx / e2) % e1, r0 = idx / (e1 * e2);
+        const int cell = ((r0 + d0 * TILE) * S + (r1 + d1 * TILE)) * S + (r2 + d2 * TILE);
+        cx<T> v;
+        if constexpr (FIXED) {
+          v = decode(accp[cell], cell);
+          if constexpr (REST) v = cadd(v, dst[base + idx]);
+        } else {
+          v = cx<T>{(T)acc[cell], (T)acc[SS + cell]};
+        }
+        dst[base + idx] = v;
+      }
     }
   }
+}
+
+template <typename T, int J, int TILE, bool CW, int DEG>
+__global__ __launch_bounds__(GridCfg<T>::NT_SPREAD)
+__attribute__((amdgpu_waves_per_eu(GridCfg<T>::SPREAD_WAVES))) void k_spread(
+    const cx<T>* __restrict__ in, cx<T>* __restrict__ partials, const int32_t* __restrict__ perm,
+    const TileTask* __restrict__ tasks, const int32_t* __restrict__ torder,
+    const float* __restrict__ bound, int32_t* __restrict__ ncls_of, XcdSplit xs, PointGeom g,
+    int nb, WeightPoly<T, DEG> P) {
+  spread_task<T, J, TILE, CW, DEG, false>(in, partials, perm, tasks, torder, bound, ncls_of, xs,
+                                          g, nb, P);
+}
+
+// FP32: the further magnitude classes of the tasks that have them
+template <typename T, int J, int TILE, bool CW, int DEG>
+__global__ __launch_bounds__(GridCfg<T>::NT_SPREAD) void k_spread_rest(
+    const cx<T>* __restrict__ in, cx<T>* __restrict__ partials, const int32_t* __restrict__ perm,
+    const TileTask* __restrict__ tasks, const int32_t* __restrict__ torder,
+    const float* __restrict__ bound, int32_t* __restrict__ ncls_of, XcdSplit xs, PointGeom g,
+    int nb, WeightPoly<T, DEG> P) {
+  spread_task<T, J, TILE, CW, DEG, true>(in, partials, perm, tasks, torder, bound, ncls_of, xs,
+                                         g, nb, P);
 }
 
 // Plan-time bound for the FP32 spreading scale: per task, the largest over
@@ -931,7 +1102,14 @@ hipError_t launch_one(const nufftct_plan& p, const void* src, void* dst, hipStre
     if constexpr (OP == OP_SPREAD) {
       hipLaunchKernelGGL((k_spread<T, J, TILE, CW, DEG>), grd, dim3(GridCfg<T>::NT_SPREAD), 0, st,
                          (const cx<T>*)src, (cx<T>*)p.d_partials, p.d_perm_s, p.d_tasks,
-                         p.d_spread_order, p.d_bound, p.xsplit, g, p.nb, P);
+                         p.d_spread_order, p.d_bound, p.d_ncls, p.xsplit, g, p.nb, P);
+      if constexpr (sizeof(T) == 4) {
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_spread_rest<T, J, TILE, CW, DEG>), grd, dim3(GridCfg<T>::NT_SPREAD),
+                           0, st, (const cx<T>*)src, (cx<T>*)p.d_partials, p.d_perm_s, p.d_tasks,
+                           p.d_spread_order, p.d_bound, p.d_ncls, p.xsplit, g, p.nb, P);
+      }
     } else if constexpr (OP == OP_BOUND) {
       hipLaunchKernelGGL((k_spread_bound<T, J, TILE, CW, DEG>), grd, dim3(NT_BOUND), 0, st,
                          p.d_bound, p.d_perm_s, p.d_tasks, p.xsplit, g, p.nb, P);

@@ -299,6 +299,7 @@ static void free_plan(nufftct_plan* p) {
   hipFree(p->d_spread_order);
   hipFree(p->d_partials);
   hipFree(p->d_bound);
+  hipFree(p->d_ncls);
   hipFree(p->d_line_w);
   hipFree(p->d_grid);
   hipFree(p->d_tmp);
@@ -346,15 +347,29 @@ static int validate(int64_t N, int64_t K, int J, int kernel, double beta, int pr
 // Autotuning of the tiling (tile edge, points per task).  Results live in a
 // process-wide table keyed by the plan's shape and are consulted by every plan
 // creation; NUFFTCT_TUNE_CACHE names an optional text file that persists them.
+// The key holds a hash of the direction (or point) coordinates, so that two
+// geometries with equal counts do not share a tiling.
 struct TuneKey {
   int64_t N, K;
   int J, kernel, precision;
   int64_t n_lines, n_r, M;
+  uint64_t geom_hash;
   bool operator==(const TuneKey& o) const {
     return N == o.N && K == o.K && J == o.J && kernel == o.kernel && precision == o.precision &&
-           n_lines == o.n_lines && n_r == o.n_r && M == o.M;
+           n_lines == o.n_lines && n_r == o.n_r && M == o.M && geom_hash == o.geom_hash;
   }
 };
+
+// FNV-1a over the bytes of the coordinates
+static uint64_t geom_hash(const double* g, int64_t n) {
+  uint64_t h = 1469598103934665603ull;
+  const unsigned char* b = reinterpret_cast<const unsigned char*>(g);
+  for (int64_t i = 0; i < n * (int64_t)sizeof(double); ++i) {
+    h ^= b[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
 struct TuneVal {
   int tile, max_pts;
 };
@@ -372,9 +387,10 @@ static void tune_load_locked() {
   TuneKey k;
   TuneVal v;
   long long a[8];
-  while (fscanf(f, "%lld %lld %lld %lld %lld %lld %lld %lld %d %d", &a[0], &a[1], &a[2], &a[3],
-                &a[4], &a[5], &a[6], &a[7], &v.tile, &v.max_pts) == 10) {
-    k = TuneKey{a[0], a[1], (int)a[2], (int)a[3], (int)a[4], a[5], a[6], a[7]};
+  unsigned long long hsh;
+  while (fscanf(f, "%lld %lld %lld %lld %lld %lld %lld %lld %llx %d %d", &a[0], &a[1], &a[2],
+                &a[3], &a[4], &a[5], &a[6], &a[7], &hsh, &v.tile, &v.max_pts) == 11) {
+    k = TuneKey{a[0], a[1], (int)a[2], (int)a[3], (int)a[4], a[5], a[6], a[7], (uint64_t)hsh};
     g_tune.push_back({k, v});
   }
   fclose(f);
@@ -399,9 +415,9 @@ static void tune_store(const TuneKey& k, const TuneVal& v) {
   if (!path || !*path) return;
   FILE* f = fopen(path, "a");
   if (!f) return;
-  fprintf(f, "%lld %lld %d %d %d %lld %lld %lld %d %d\n", (long long)k.N, (long long)k.K, k.J,
-          k.kernel, k.precision, (long long)k.n_lines, (long long)k.n_r, (long long)k.M, v.tile,
-          v.max_pts);
+  fprintf(f, "%lld %lld %d %d %d %lld %lld %lld %llx %d %d\n", (long long)k.N, (long long)k.K,
+          k.J, k.kernel, k.precision, (long long)k.n_lines, (long long)k.n_r, (long long)k.M,
+          (unsigned long long)k.geom_hash, v.tile, v.max_pts);
   fclose(f);
 }
 
@@ -435,7 +451,7 @@ static int create(nufftct_plan** out, int64_t N, int64_t K, int J, int kernel, d
   // (tile + J - 1)^3 cells fits in LDS
   // order of precedence: explicit request (autotuner) > environment > tuned
   // table > default
-  TuneKey tkey{N, K, J, kernel, precision, p->n_lines, n_r, M};
+  TuneKey tkey{N, K, J, kernel, precision, p->n_lines, n_r, M, geom_hash(geom, 3 * n_geom)};
   TuneVal tuned{0, 0};
   const bool have_tuned = tune_lookup(tkey, &tuned);
   {
@@ -644,6 +660,7 @@ static int create(nufftct_plan** out, int64_t N, int64_t K, int J, int kernel, d
   if (precision == NUFFTCT_FP32) {
     const size_t bbytes = (size_t)std::max<int64_t>(p->ntasks, 1) * sizeof(float);
     hipError_t e = hipMalloc(&p->d_bound, bbytes);
+    if (e == hipSuccess) e = hipMalloc(&p->d_ncls, (size_t)std::max<int64_t>(p->ntasks, 1) * sizeof(int32_t));
     if (e != hipSuccess) {
       free_plan(p);
       return fail(NUFFTCT_ENOMEM, "spread bounds of %zu bytes: %s", bbytes, hipGetErrorString(e));
@@ -826,10 +843,16 @@ int nufftct_autotune_radial(int64_t N, int64_t K, int J, int kernel, double beta
     return fail(NUFFTCT_ENOMEM, "autotune buffers");
   }
   // any non-zero pattern: the run time does not depend on the values
-  hipMemsetAsync(vol, 0x3c, (size_t)N * N * N * cxb, st);
-  hipEvent_t e0, e1;
-  hipEventCreate(&e0);
-  hipEventCreate(&e1);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t he = hipMemsetAsync(vol, 0x3c, (size_t)N * N * N * cxb, st);
+  if (he == hipSuccess) he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  if (he != hipSuccess) {
+    if (e0) hipEventDestroy(e0);
+    hipFree(vol);
+    hipFree(out);
+    return fail(NUFFTCT_EHIP, "autotune set-up: %s", hipGetErrorString(he));
+  }
   const int tiles[2] = {16, 8};
   const int mps[6] = {1024, 2048, 4096, 8192, 12288, 16384};
   double best = 1e30;
@@ -845,27 +868,34 @@ int nufftct_autotune_radial(int64_t N, int64_t K, int J, int kernel, double beta
       }
       int rc = nufftct_forward(p, vol, out, flags, stream);
       if (!rc) rc = nufftct_adjoint(p, out, vol, flags, stream);
-      hipEventRecord(e0, st);
+      if (!rc && hipEventRecord(e0, st) != hipSuccess) rc = NUFFTCT_EHIP;
       for (int r = 0; r < 2 && !rc; ++r) {
         rc = nufftct_forward(p, vol, out, flags, stream);
         if (!rc) rc = nufftct_adjoint(p, out, vol, flags, stream);
       }
-      hipEventRecord(e1, st);
+      if (!rc && hipEventRecord(e1, st) != hipSuccess) rc = NUFFTCT_EHIP;
       float ms = 0;
       if (!rc && hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess &&
           ms / 2 < best) {
         best = ms / 2;
         bv = TuneVal{t, mp};
       }
-      hipStreamSynchronize(st);
+      const hipError_t se = hipStreamSynchronize(st);
       free_plan(p);
+      if (se != hipSuccess) {  // a fault of a candidate: stop tuning
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        hipFree(vol);
+        hipFree(out);
+        return fail(NUFFTCT_EHIP, "autotune candidate failed: %s", hipGetErrorString(se));
+      }
     }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   hipFree(vol);
   hipFree(out);
   if (bv.tile == 0) return fail(NUFFTCT_EHIP, "no autotune candidate ran");
-  tune_store(TuneKey{N, K, J, kernel, precision, n_lines, n_r, M}, bv);
+  tune_store(TuneKey{N, K, J, kernel, precision, n_lines, n_r, M, geom_hash(dirs, 3 * n_lines)}, bv);
   if (best_tile) *best_tile = bv.tile;
   if (best_max_pts) *best_max_pts = bv.max_pts;
   if (best_ms) *best_ms = best;
@@ -991,6 +1021,13 @@ int nufftct_plan_info(const nufftct_plan* p, int64_t* N, int64_t* K, int* J, int
   if (n_r) *n_r = p->n_r;
   if (precision) *precision = p->precision;
   if (workspace_bytes) *workspace_bytes = (int64_t)(p->grid_bytes + p->tmp_bytes + p->partial_bytes);
+  return NUFFTCT_OK;
+}
+
+int nufftct_plan_tiling(const nufftct_plan* p, int* tile, int* max_pts) {
+  if (!p) return fail(NUFFTCT_EINVAL, "plan is NULL");
+  if (tile) *tile = p->tile;
+  if (max_pts) *max_pts = p->max_pts;
   return NUFFTCT_OK;
 }
 

@@ -74,6 +74,7 @@ struct nufftct_plan {
   int32_t* d_spread_order = nullptr; // ntasks: spreading dispatch order (per XCD range, largest first)
   void* d_partials = nullptr;      // per task, its spread halo tile (S^3 complex)
   float* d_bound = nullptr;        // FP32: per task, max over halo cells of sum |w|
+  int32_t* d_ncls = nullptr;       // FP32: per task, 1 or 2 (further magnitude classes follow)
   double* d_line_w = nullptr;      // radial plans: per-line reconstruction weights (optional)
   void* d_grid = nullptr;       // K^3 complex workspace
   void* d_tmp = nullptr;        // M complex workspace

@@ -3,6 +3,10 @@ FP64 oracle, through the C ABI (python binding = argument marshalling only).
 
 Bars: FP32 path <= 1e-5 relative L2 against the oracle with the same kernel
 and grid; FP64 form <= 1e-12; <= 1e-4 against the exact NUDFT at J=6, K=2N.
+Every relative-L2 bar comes with the same bar on the max error
+max|a - ref| / max|ref|.  The grid and line lengths cover every radix plan of
+the workloads: 16..96, and 192 = 8 8 3, 256 = 8 8 4, 320 = 8 8 5 (the c2, c4
+and c5 grids; the last three with few lines, so the oracle stays fast).
 """
 import math
 import zlib
@@ -38,7 +42,20 @@ CASES = [
     ("n32_k64_j6_minmax", 32, 64, 6, "minmax", 8, 4, 64),
     ("n24_k48_j6_fewlines", 24, 48, 6, "kb", 5, 5, 48),
     ("n8_k16_j4_onetile", 8, 16, 4, "kb", 4, 3, 16),
+    ("n96_k192_j6_radix3", 96, 192, 6, "kb", 6, 3, 192),
+    ("n128_k256_j6_c2grid", 128, 256, 6, "kb", 6, 3, 256),
+    ("n160_k320_j6_radix5", 160, 320, 6, "kb", 4, 3, 320),
 ]
+# cases whose oracle transforms are large: one flag mode in the full-operator test
+BIG_K = 192
+
+
+def check(name, got, want, rel_bar, max_bar=None):
+    """Relative L2 and max error (max|a - ref| / max|ref|) against their bars."""
+    e, m = rel_l2(got, want), max_rel(got, want)
+    say(f"{name} rel={e:.2e} max={m:.2e}")
+    assert e < rel_bar and m < (rel_bar if max_bar is None else max_bar), (name, e, m)
+    return e
 
 
 def f64_tol(S, base):
@@ -82,9 +99,8 @@ def test_stage_pad_fft(S):
     g = torch.empty(S.K ** 3, dtype=_torch_dtype(S.prec), device="cuda")
     S.plan.stage(0, to_dev(S.x, _torch_dtype(S.prec)), g)
     want = np.fft.fftshift(nufft.oversampled_spectrum(S.x, S.prm))  # centred layout
-    err = rel_l2(to_host(g).reshape(want.shape), want)
-    say(f"pad_fft {S.name} {S.prec} rel={err:.2e}")
-    assert err < (2e-6 if S.prec == "f32" else 1e-13)
+    check(f"pad_fft {S.name} {S.prec}", to_host(g).reshape(want.shape), want,
+          2e-6 if S.prec == "f32" else 1e-13)
 
 
 def test_stage_interp(S):
@@ -94,9 +110,8 @@ def test_stage_interp(S):
     out = torch.empty(S.M, dtype=_torch_dtype(S.prec), device="cuda")
     S.plan.stage(1, to_dev(Yd, _torch_dtype(S.prec)), out)
     want = nufft.interpolate(np.fft.ifftshift(Yd.astype(np.complex128)), S.om, S.prm)
-    err = rel_l2(to_host(out), want)
-    say(f"interp {S.name} {S.prec} rel={err:.2e} max={max_rel(to_host(out), want):.2e}")
-    assert err < (1e-6 if S.prec == "f32" else f64_tol(S, 1e-13))
+    check(f"interp {S.name} {S.prec}", to_host(out), want,
+          1e-6 if S.prec == "f32" else f64_tol(S, 1e-13))
 
 
 @pytest.mark.parametrize("deriv", [True, False])
@@ -104,12 +119,13 @@ def test_stage_radial(S, deriv):
     import torch
     td = _torch_dtype(S.prec)
     out = torch.empty(S.M, dtype=td, device="cuda")
+    bar = 1e-6 if S.prec == "f32" else 1e-14
     S.plan.stage(2, to_dev(S.y, td), out, deriv=deriv)
-    want = radial.forward(S.y, S.n_r, deriv)
-    assert rel_l2(to_host(out), want) < (1e-6 if S.prec == "f32" else 1e-14)
+    check(f"radial {S.name} {S.prec} deriv={deriv}", to_host(out),
+          radial.forward(S.y, S.n_r, deriv), bar)
     S.plan.stage(3, to_dev(S.y, td), out, deriv=deriv)
-    want = radial.adjoint(S.y, S.n_r, deriv)
-    assert rel_l2(to_host(out), want) < (1e-6 if S.prec == "f32" else 1e-14)
+    check(f"radial_adj {S.name} {S.prec} deriv={deriv}", to_host(out),
+          radial.adjoint(S.y, S.n_r, deriv), bar)
 
 
 def test_stage_spread(S):
@@ -118,9 +134,8 @@ def test_stage_spread(S):
     g = torch.empty(S.K ** 3, dtype=td, device="cuda")
     S.plan.stage(4, to_dev(S.y, td), g)
     want = np.fft.fftshift(nufft.spread(S.y, S.om, S.prm))
-    err = rel_l2(to_host(g).reshape(want.shape), want)
-    say(f"spread {S.name} {S.prec} rel={err:.2e}")
-    assert err < (2e-6 if S.prec == "f32" else f64_tol(S, 1e-13))
+    check(f"spread {S.name} {S.prec}", to_host(g).reshape(want.shape), want,
+          2e-6 if S.prec == "f32" else f64_tol(S, 1e-13))
 
 
 def test_stage_ifft_crop(S):
@@ -134,25 +149,24 @@ def test_stage_ifft_crop(S):
     S.plan.stage(5, gd, v)
     assert torch.equal(gd, before), "stage must not modify its input"
     want = nufft.crop_scale(nufft.inverse_spectrum(np.fft.ifftshift(G.astype(np.complex128)), S.prm), S.prm)
-    err = rel_l2(to_host(v).reshape(want.shape), want)
-    say(f"ifft_crop {S.name} {S.prec} rel={err:.2e}")
-    assert err < (2e-6 if S.prec == "f32" else 1e-13)
+    check(f"ifft_crop {S.name} {S.prec}", to_host(v).reshape(want.shape), want,
+          2e-6 if S.prec == "f32" else 1e-13)
 
 
 @pytest.mark.parametrize("flags", ["deriv_radial", "radial", "plain"])
 def test_forward_adjoint_vs_oracle(S, flags):
+    if S.K >= BIG_K and flags != "deriv_radial":
+        pytest.skip("large grid: the derivative-Radon mode covers the operator")
     td = _torch_dtype(S.prec)
     rad = flags != "plain"
     der = flags == "deriv_radial"
+    tol = TOL["f32"] if S.prec == "f32" else f64_tol(S, TOL["f64"])
     out = S.plan.forward(to_dev(S.x, td), radial=rad, deriv=der)
     want = projector.forward(S.x, S.dirs, S.n_r, S.prm, deriv=der, radial_stage=rad)
-    ef = rel_l2(to_host(out), want)
+    check(f"full fwd {S.name} {S.prec} {flags}", to_host(out), want, tol)
     vol = S.plan.adjoint(to_dev(S.y, td), radial=rad, deriv=der)
     want_a = projector.adjoint(S.y, S.dirs, S.n_r, S.prm, deriv=der, radial_stage=rad)
-    ea = rel_l2(to_host(vol), want_a)
-    say(f"full {S.name} {S.prec} {flags} fwd={ef:.2e} adj={ea:.2e}")
-    tol = TOL["f32"] if S.prec == "f32" else f64_tol(S, TOL["f64"])
-    assert ef < tol and ea < tol
+    check(f"full adj {S.name} {S.prec} {flags}", to_host(vol), want_a, tol)
 
 
 def test_dot_product(S):
@@ -175,6 +189,17 @@ def test_forward_deterministic(S):
     assert torch.equal(a, b)
 
 
+def test_adjoint_deterministic_fp32(S):
+    """The FP32 spreading sums integers, so the adjoint is bitwise reproducible."""
+    import torch
+    if S.prec != "f32":
+        pytest.skip("FP32 path")
+    yd = to_dev(S.y, _torch_dtype(S.prec))
+    a = S.plan.adjoint(yd)
+    for _ in range(3):
+        assert torch.equal(a, S.plan.adjoint(yd))
+
+
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_point_plan_random_and_edges(prec):
@@ -194,9 +219,9 @@ def test_point_plan_random_and_edges(prec):
     y = (rng.standard_normal(len(om)) + 1j * rng.standard_normal(len(om))).astype(_np_dtype(prec)).astype(complex)
     f = to_host(plan.forward(to_dev(x, td)))
     a = to_host(plan.adjoint(to_dev(y, td)))
-    assert rel_l2(f, nufft.forward(x, om, prm)) < TOL[prec]
-    assert rel_l2(a, nufft.adjoint(y, om, prm)) < TOL[prec]
-    assert rel_l2(f, nudft.nudft3(x, om)) < 1e-4
+    check(f"points fwd {prec}", f, nufft.forward(x, om, prm), TOL[prec])
+    check(f"points adj {prec}", a, nufft.adjoint(y, om, prm), TOL[prec])
+    check(f"points vs NUDFT {prec}", f, nudft.nudft3(x, om), 1e-4)
 
 
 @pytest.mark.parametrize("M", [1, 7, 257])
@@ -211,8 +236,8 @@ def test_tiny_point_sets(M):
     prm = nufft.Params(N, K, J)
     x = rng.standard_normal((N,) * 3) + 0j
     y = rng.standard_normal(M) + 1j * rng.standard_normal(M)
-    assert rel_l2(to_host(plan.forward(to_dev(x, torch.complex128))), nufft.forward(x, om, prm)) < 1e-12
-    assert rel_l2(to_host(plan.adjoint(to_dev(y, torch.complex128))), nufft.adjoint(y, om, prm)) < 1e-12
+    check(f"tiny fwd M={M}", to_host(plan.forward(to_dev(x, torch.complex128))), nufft.forward(x, om, prm), 1e-12)
+    check(f"tiny adj M={M}", to_host(plan.adjoint(to_dev(y, torch.complex128))), nufft.adjoint(y, om, prm), 1e-12)
 
 
 def test_single_line_and_zero_input():
@@ -229,7 +254,7 @@ def test_single_line_and_zero_input():
     x = synthetic.gaussian_blob(N, np.array([0.5, -0.5, 1.0]), np.diag([3.0, 3.0, 3.0]))
     d = to_host(plan.forward(to_dev(x.astype(np.complex64), torch.complex64), deriv=False))
     want = projector.forward(x, dirs, n_r, nufft.Params(N, K, J), deriv=False)
-    assert rel_l2(d, want) < 1e-5
+    check("single line", d, want, 1e-5)
 
 
 def test_vs_exact_nudft_j6():
@@ -244,9 +269,7 @@ def test_vs_exact_nudft_j6():
     G = to_host(plan.forward(to_dev(x.astype(np.complex64), torch.complex64), radial=False)).reshape(-1)
     sel = np.random.default_rng(3).choice(len(G), 3000, replace=False)
     exact = nudft.nudft3(x, radial.points(dirs, n_r)[sel])
-    err = rel_l2(G[sel], exact)
-    say(f"vs NUDFT {err:.2e}")
-    assert err < 1e-4
+    check("vs NUDFT J=6", G[sel], exact, 1e-4)
 
 
 def test_python_binding_rejects_bad_tensors():
@@ -283,10 +306,8 @@ def test_tiling_and_split_tiles(monkeypatch, tile, maxpts):
     plan = Plan(N, K, J, dirs=dirs, n_r=n_r)
     f = to_host(plan.forward(to_dev(x, torch.complex64)))
     a = to_host(plan.adjoint(to_dev(y, torch.complex64)))
-    ef = rel_l2(f, projector.forward(x, dirs, n_r, prm))
-    ea = rel_l2(a, projector.adjoint(y, dirs, n_r, prm))
-    say(f"tile={tile} maxpts={maxpts} fwd={ef:.2e} adj={ea:.2e}")
-    assert ef < 1e-5 and ea < 1e-5
+    check(f"tile={tile} maxpts={maxpts} fwd", f, projector.forward(x, dirs, n_r, prm), 1e-5)
+    check(f"tile={tile} maxpts={maxpts} adj", a, projector.adjoint(y, dirs, n_r, prm), 1e-5)
 
 
 def test_autotune_records_and_is_used():
@@ -297,9 +318,11 @@ def test_autotune_records_and_is_used():
     dirs = synthetic.line_directions(synthetic.azimuths(20), synthetic.polar_angles(10))
     r = pkg.autotune(N, K, J, dirs, n_r)
     say(f"autotune {r}")
-    assert r["tile"] in (8, 16) and r["max_pts"] in (1024, 2048, 4096, 8192) and r["ms"] > 0
+    assert r["tile"] in (8, 16) and r["max_pts"] >= 256 and r["ms"] > 0
     plan = pkg.Plan(N, K, J, dirs=dirs, n_r=n_r)
+    # the recorded tiling is the one later plans of this shape use
+    assert plan.tiling() == (r["tile"], r["max_pts"])
     prm = nufft.Params(N, K, J)
     x = synthetic.ellipsoid_phantom(N, 6, 9).astype(np.complex64).astype(complex)
     f = to_host(plan.forward(to_dev(x, torch.complex64)))
-    assert rel_l2(f, projector.forward(x, dirs, n_r, prm)) < 1e-5
+    check("autotuned fwd", f, projector.forward(x, dirs, n_r, prm), 1e-5)
