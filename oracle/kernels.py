@@ -66,16 +66,23 @@ def deapod(N: int, K: int, J: int, beta: float) -> np.ndarray:
 def neighbours(omega_d: np.ndarray, K: int, J: int):
     """Neighbour rule for one axis.
 
-    Returns (kappa, u): kappa[p, j] = k0 + j + 1 (integers, not yet wrapped),
-    u[p, j] = t - kappa[p, j], with t = omega / (2 pi / K) and
-    k0 = floor(t - J/2), all in FP64.
+    Returns (kappa, u): kappa[p, j] = k0 + j + 1 (integers, not yet wrapped)
+    and the offsets u[p, j] = t - kappa[p, j], with t = omega / (2 pi / K),
+    all in FP64.  The taps and the offsets both come from the one rounded
+    value s = t - J/2: k0 = floor(s), frac = s - k0 (exact, in [0, 1)) and
+    u = J/2 + frac - (j + 1).  The offsets then lie in [-J/2, J/2) as they do
+    in exact arithmetic; forming t - kappa from the unrounded t instead can
+    put the last offset just below -J/2 where s rounded onto an integer,
+    outside the kernel's support.
     """
     gamma = TWO_PI / K
     t = np.asarray(omega_d, dtype=np.float64) / gamma
-    k0 = np.floor(t - J / 2)
+    s = t - J / 2
+    k0 = np.floor(s)
+    frac = s - k0
     j = np.arange(1, J + 1, dtype=np.float64)
     kappa = k0[:, None] + j[None, :]
-    u = t[:, None] - kappa
+    u = (J / 2 - j)[None, :] + frac[:, None]
     return kappa.astype(np.int64), u
 
 

@@ -702,6 +702,9 @@ __device__ __forceinline__ void spread_task(const cx<T>* __restrict__ in,
       const bool bad2 = FIXED && !REST && bad && pair && nonfinite(v2);
       v = prep(v);
       v2 = prep(v2);
+      const bool nz1 = v.x != (T)0 || v.y != (T)0, nz2 = pair && (v2.x != (T)0 || v2.y != (T)0);
+      // nothing to add (zero values, or values of other classes) and nothing to flag
+      if (!nz1 && !nz2 && !bad1 && !bad2) continue;
       int first[3], first2[3] = {0, 0, 0};
       double frac[3], frac2[3] = {0.0, 0.0, 0.0};
       point_taps<sizeof(T) == 4>(g, cur, J, first, frac);
@@ -726,7 +729,6 @@ __device__ __forceinline__ void spread_task(const cx<T>* __restrict__ in,
         if (bad1 && in1) flag_footprint<J, S>(s_nan, (l0 * S + l1) * S + l2);
         if (bad2 && in2) flag_footprint<J, S>(s_nan, (m0 * S + m1) * S + m2);
       }
-      const bool nz1 = v.x != (T)0 || v.y != (T)0, nz2 = pair && (v2.x != (T)0 || v2.y != (T)0);
       if constexpr (PAIRED) {
         // (a single point, or a pair whose first cells differ, adds a zero here)
         const bool both = pair && same;

@@ -60,6 +60,26 @@ def test_neighbour_rule():
     assert kap[0].tolist() == [-2, -1, 0, 1, 2, 3]
 
 
+def test_neighbour_offsets_stay_in_support_when_s_rounds():
+    """Where s = t - J/2 rounds onto an integer (t just beyond a negative
+    integer, where t - J/2 enters a coarser binade), the taps follow the
+    rounded s and so must the offsets: all J of them inside [-J/2, J/2), so
+    that no tap's weight falls off the kernel's support (psi = 0 there)."""
+    K, J = 192, 6
+    gamma = 2 * math.pi / K
+    ts = np.array([-3.0000000000000004, -2.0000000000000004, -1.0000000000000002,
+                   -5.000000000000001, -3.9999999999999996])
+    kap, u = kernels.neighbours(ts * gamma, K, J)
+    t = (ts * gamma) / gamma
+    for p in range(len(ts)):
+        s = t[p] - J / 2
+        assert kap[p].tolist() == list(range(int(math.floor(s)) + 1, int(math.floor(s)) + J + 1))
+        assert np.all(u[p] >= -J / 2) and np.all(u[p] < J / 2), (ts[p], u[p])
+        assert np.all(kernels.kb_psi(u[p], J, kernels.default_beta(J)) > 0)
+    # the first case rounds: s = -6 exactly although t - 3 < -6
+    assert t[0] - 3 == -6.0 and t[0] < -3.0
+
+
 def test_minmax_reproduces_exponential_at_uniform_full_width(rng):
     # J = K = N with s = 1: the fit is exact (periodic sinc interpolation, eq 2.2-2.7)
     N = K = J = 8
