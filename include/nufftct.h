@@ -81,6 +81,12 @@ typedef struct nufftct_umbrella nufftct_umbrella;
 #define NUFFTCT_RADIAL 1 /* apply the per-line radial (inverse) DFT stage */
 #define NUFFTCT_DERIV 2  /* with RADIAL: include the i*r derivative factor */
 #define NUFFTCT_DERIV_RADIAL 3
+/* adjoint: bitwise reproducible spreading.  The FP32 path always spreads in
+ * fixed point (integer sums do not depend on the order of the atomic adds);
+ * with this flag the FP64 form does too (64-bit words, scale 2^62 / (vmax B)
+ * per task), instead of FP64 atomic adds whose rounding follows their order.
+ * Accepted, and without effect, by the forward operator. */
+#define NUFFTCT_DETERMINISTIC 4
 
 /* stages for nufftct_stage (one stage of the path, for testing and profiling) */
 #define NUFFTCT_STAGE_PAD_FFT 0   /* vol[N^3]  -> grid[K^3] centred spectrum (F1+F2) */
@@ -149,7 +155,9 @@ int nufftct_forward(nufftct_plan* plan, const void* vol, void* out, int flags, v
 
 /*
  * Adjoint (exact conjugate transpose of nufftct_forward with the same flags):
- * in (device, M complex) -> vol (device, N^3 complex, overwritten).
+ * in (device, M complex) -> vol (device, N^3 complex, overwritten).  With
+ * NUFFTCT_DETERMINISTIC in flags the result is bitwise reproducible in both
+ * precisions (the FP32 path always is).
  */
 int nufftct_adjoint(nufftct_plan* plan, const void* in, void* vol, int flags, void* stream);
 

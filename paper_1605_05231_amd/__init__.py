@@ -13,7 +13,7 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import (DERIV, DERIV_RADIAL, FP32, FP64, KERNEL_KB, KERNEL_MINMAX_KB, RADIAL,  # noqa: F401
+from ._lib import (DERIV, DERIV_RADIAL, DETERMINISTIC, FP32, FP64, KERNEL_KB, KERNEL_MINMAX_KB, RADIAL,  # noqa: F401
                    STAGE_IFFT_CROP, STAGE_INTERP, STAGE_NAMES, STAGE_PAD_FFT, STAGE_RADIAL,
                    STAGE_RADIAL_ADJ, STAGE_SPREAD, NufftError)
 
@@ -147,8 +147,11 @@ class Plan:
                                                C.c_void_p(_stream_handle(stream))))
         return out
 
-    def adjoint(self, y, out=None, *, radial: bool = True, deriv: bool = True, stream=None):
-        """(L, n_r) or (M,) -> vol (N,N,N): exact conjugate transpose of forward."""
+    def adjoint(self, y, out=None, *, radial: bool = True, deriv: bool = True,
+                deterministic: bool = False, stream=None):
+        """(L, n_r) or (M,) -> vol (N,N,N): exact conjugate transpose of forward.
+        deterministic: bitwise reproducible in the FP64 form too (the FP32
+        path always is)."""
         torch = _torch()
         radial = radial and self.n_r > 0
         _check_tensor(y, self.M, self.dtype, "y")
@@ -156,7 +159,8 @@ class Plan:
             out = torch.empty(self.vol_shape, dtype=self.dtype, device=y.device)
         _check_tensor(out, self.N ** 3, self.dtype, "out")
         _lib.check(_lib.load().nufftct_adjoint(self._ptr, y.data_ptr(), out.data_ptr(),
-                                               self._flags(radial, deriv),
+                                               self._flags(radial, deriv)
+                                               | (DETERMINISTIC if deterministic else 0),
                                                C.c_void_p(_stream_handle(stream))))
         return out
 
@@ -180,7 +184,8 @@ class Plan:
                                                    C.c_void_p(_stream_handle(stream))))
         return out
 
-    def stage(self, stage: int, inp, out, *, deriv: bool = True, stream=None):
+    def stage(self, stage: int, inp, out, *, deriv: bool = True, deterministic: bool = False,
+              stream=None):
         """Run a single stage (STAGE_*); sizes: vol N^3, grid K^3, points M."""
         sizes = {STAGE_PAD_FFT: (self.N ** 3, self.K ** 3), STAGE_INTERP: (self.K ** 3, self.M),
                  STAGE_RADIAL: (self.M, self.M), STAGE_RADIAL_ADJ: (self.M, self.M),
@@ -189,7 +194,8 @@ class Plan:
         _check_tensor(inp, ni, self.dtype, "inp")
         _check_tensor(out, no, self.dtype, "out")
         _lib.check(_lib.load().nufftct_stage(self._ptr, stage, inp.data_ptr(), out.data_ptr(),
-                                             DERIV if deriv else 0,
+                                             (DERIV if deriv else 0)
+                                             | (DETERMINISTIC if deterministic else 0),
                                              C.c_void_p(_stream_handle(stream))))
         return out
 

@@ -12,6 +12,7 @@ KERNEL_KB, KERNEL_MINMAX_KB = 0, 1
 FP32, FP64 = 0, 1
 RADIAL, DERIV = 1, 2
 DERIV_RADIAL = RADIAL | DERIV
+DETERMINISTIC = 4
 STAGE_PAD_FFT, STAGE_INTERP, STAGE_RADIAL, STAGE_RADIAL_ADJ, STAGE_SPREAD, STAGE_IFFT_CROP = range(6)
 STAGE_NAMES = ["pad_fft", "interp", "radial", "radial_adj", "spread", "ifft_crop", "merge"]
 TIMING_MERGE = 6

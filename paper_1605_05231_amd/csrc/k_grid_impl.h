@@ -394,16 +394,20 @@ __attribute__((amdgpu_waves_per_eu(GridCfg<T>::INTERP_WAVES))) void k_interp(con
   }
 }
 
-// One contribution u to halo cell `cell` of the task's LDS accumulators:
-// FP32 packs the rounded components into one 64-bit word (q_re 2^32 + q_im,
-// the high half less the borrow of a negative q_im); FP64 adds to planar
-// accumulators.
-template <typename T, int SS>
+// One contribution u (already on the fixed-point scale when FIXED) to halo
+// cell `cell` of the task's LDS accumulators: FP32 packs the rounded
+// components into one 64-bit word (q_re 2^32 + q_im, the high half less the
+// borrow of a negative q_im); FP64 fixed point adds each rounded component
+// to its own 64-bit word; FP64 floating point adds to planar accumulators.
+template <typename T, int SS, bool FIXED>
 __device__ __forceinline__ void add_cell(unsigned long long* accp, double* acc, int cell, cx<T> u) {
   if constexpr (sizeof(T) == 4) {
     const int qr = round_int(u.x), qi = round_int(u.y);
     const unsigned int hi = (unsigned int)qr + (unsigned int)(qi >> 31);
     lds_add(&accp[cell], ((unsigned long long)hi << 32) | (unsigned int)qi);
+  } else if constexpr (FIXED) {
+    lds_add(&accp[cell], (unsigned long long)(long long)rint((double)u.x));
+    lds_add(&accp[SS + cell], (unsigned long long)(long long)rint((double)u.y));
   } else {
     lds_add(&acc[cell], (double)u.x);
     lds_add(&acc[SS + cell], (double)u.y);
@@ -412,7 +416,7 @@ __device__ __forceinline__ void add_cell(unsigned long long* accp, double* acc, 
 
 // The J^3 contributions of one point (value v, tap (0,0,0) at halo cell
 // `base`), with conj(w) for the transpose.
-template <typename T, int J, int S, int SS, bool CW>
+template <typename T, int J, int S, int SS, bool CW, bool FIXED>
 __device__ __forceinline__ void spread_one(unsigned long long* accp, double* acc, cx<T> v, int base,
                                            const T (&w0r)[J], const T (&w0i)[J],
                                            const T (&w1r)[J], const T (&w1i)[J],
@@ -429,7 +433,7 @@ __device__ __forceinline__ void spread_one(unsigned long long* accp, double* acc
       for (int c = 0; c < J; ++c) {
         const cx<T> u =
             CW ? cmulc(vb, cx<T>{w2r[c], w2i[c]}) : cx<T>{w2r[c] * vb.x, w2r[c] * vb.y};
-        add_cell<T, SS>(accp, acc, row + c, u);
+        add_cell<T, SS, FIXED>(accp, acc, row + c, u);
       }
     }
   }
@@ -437,7 +441,7 @@ __device__ __forceinline__ void spread_one(unsigned long long* accp, double* acc
 
 // Two points with the same first tap cell and real weights w and x: each of
 // the J^3 cells receives w v + x v2 in one atomic.
-template <typename T, int J, int S, int SS>
+template <typename T, int J, int S, int SS, bool FIXED>
 __device__ __forceinline__ void spread_pair(unsigned long long* accp, double* acc, cx<T> v,
                                             cx<T> v2, int base, const T (&w0r)[J],
                                             const T (&w1r)[J], const T (&w2r)[J],
@@ -453,7 +457,7 @@ __device__ __forceinline__ void spread_pair(unsigned long long* accp, double* ac
 #pragma unroll
       for (int c = 0; c < J; ++c) {
         const cx<T> u = {w2r[c] * vb.x + x2r[c] * xb.x, w2r[c] * vb.y + x2r[c] * xb.y};
-        add_cell<T, SS>(accp, acc, row + c, u);
+        add_cell<T, SS, FIXED>(accp, acc, row + c, u);
       }
     }
   }
@@ -466,39 +470,71 @@ __device__ __forceinline__ void spread_pair(unsigned long long* accp, double* ac
 // point is visited once and every tap lands inside the halo.
 //
 // LDS accumulation (f32 LDS atomic adds run ~8x slower than 64-bit ones on
-// gfx950):
-//   FP32 path: exact integer sums, both components in one 64-bit word.  A
-//     value v of magnitude a = max(|re v|, |im v|) is scaled to
-//     s v = 2^-c f v with f = 2^30 / (u B) (2^29 for complex weights), where
-//     u 2^c bounds the magnitudes of its class (below) and B is the plan-time
-//     bound on sum_points prod_axes |w| at any cell of the halo
-//     (k_spread_bound); every cell's sums of rounded contributions
-//     q = floor(s u + 1/2) then stay inside [-2^31, 2^31).  Each tap adds the
-//     word q_re 2^32 + q_im (two's complement) with one ds_add_u64; the low
-//     half of a sum is the sum of q_im and the rest the sum of q_re, the
-//     carries between them being exact.  The per-contribution error is
-//     <= 0.5 / s, and the sum does not depend on the order of the atomics
-//     (bitwise reproducible).  The scaling by 2^-c is exact (ldexp) and the
-//     decoding runs in FP64, so tiny and huge magnitudes keep their precision.
+// gfx950), fixed point in integers, order-independent and so bitwise
+// reproducible:
+//   FP32 path: both components in one 64-bit word.  With the task's scale
+//     s = 2^30 / (vmax B) (2^29 for complex weights), vmax the largest
+//     component of the task's values and B the plan-time bound on
+//     sum_points prod_axes |w| at any cell of the halo (k_spread_bound),
+//     every cell's sums of the rounded contributions q = floor(s u + 1/2)
+//     stay inside [-2^31, 2^31).  Each tap adds the word q_re 2^32 + q_im
+//     (two's complement) with one ds_add_u64; the low half of a sum is the
+//     sum of q_im and the rest the sum of q_re, the carries between them being
+//     exact.  The per-contribution error is <= 0.5 / s.
+//   FP64 form, deterministic mode: one 64-bit word per component, scale
+//     2^62 / (vmax B) (2^61 for complex weights), one ds_add_u64 each.
+//   FP64 form, default: FP64 atomic adds (ds_add_f64) on planar real /
+//     imaginary accumulators (order-dependent rounding).
+// The fixed-point kernels run in two passes.  The main kernel spreads every
+// task whose values need nothing more than that single scale; a task whose
+// non-zero magnitudes span 2^CLASS_BITS or more, whose scale is not a normal
+// number (magnitudes near the ends of the range), or that holds a NaN or an
+// infinity goes on a list, and a second kernel spreads the listed tasks in
+// full:
 //   Magnitude classes: the error bound follows the largest magnitude that
-//     shares the scale, so a task whose non-zero magnitudes span more than
-//     2^CLASS_BITS is spread in several passes, one per class of binades
-//     (each class holds the occupied binades within CLASS_BITS of its top),
-//     each with its own scale; later passes add their decoded sums to the
+//     shares the scale, so such a task is spread in several passes, one per
+//     class of binades (each class holds the occupied binades within
+//     CLASS_BITS of its top) with its own scale 2^-c f (2^c the class's bound,
+//     applied exactly with ldexp, so tiny and huge magnitudes keep their
+//     precision); the passes after the first add their decoded sums to the
 //     partial.  A value's contributions are then accurate to
-//     <= 2^(CLASS_BITS - 30) B times its own magnitude (one pass, and the
-//     task maximum itself as the bound, in the usual case).
-//   Non-finite values: they take no part in the integer sums; the cells of
-//     their J^3 footprints are flagged and written as NaN.
-//   FP64 form: FP64 atomic adds (ds_add_f64) on planar real / imaginary
-//     accumulators.
-constexpr int CLASS_BITS = 12;
-constexpr int MAX_CLASSES = 32;  // finite non-zero floats span 277 binades
-constexpr int EXP_OFF = 148;     // frexp exponents of finite floats: [-148, 128]
-constexpr int EXP_WORDS = 9;     // occupancy bits of those 277 exponents
+//     <= 2^(CLASS_BITS - 31) B times twice its own magnitude.
+//   Non-finite values take no part in the integer sums; the cells of their
+//     J^3 footprints are flagged and written as NaN.
+constexpr int CLASS_BITS = 16;
+constexpr int MAX_CLASSES = 96;  // finite non-zero doubles span 2098 binades: 175 classes at most
+                                 // of which the class list keeps the top 96 (floats need 22)
 
-// binary exponent e of a > 0 (a in [2^(e-1), 2^e)), denormals included
-__device__ __forceinline__ int exp_of(float a) { return __builtin_amdgcn_frexp_expf(a); }
+template <typename T>
+struct Mag;
+template <>
+struct Mag<float> {  // magnitudes of FP32 values by their bit patterns
+  using U = unsigned;
+  static constexpr float MAXV = 3.402823466e38f;
+  static constexpr int EXP_OFF = 126, EXP_WORDS = 8;  // exponents [-126, 128]
+  static constexpr double RANGE = 1073741824.0;        // 2^30
+  // binary exponent e with a < 2^e (a in [2^(e-1), 2^e) for normal values;
+  // denormals and zero give the smallest binade's bound)
+  __device__ static int exp_of(float a) { return (int)(__float_as_uint(a) >> 23) - 126; }
+  __device__ static U bits(float a) { return __float_as_uint(a); }
+  __device__ static float from(U b) { return __uint_as_float(b); }
+  __device__ static float ldexp2(float x, int e) { return ldexpf(x, e); }  // exact
+  static constexpr U NONE = 0xffffffffu;
+};
+template <>
+struct Mag<double> {
+  using U = unsigned long long;
+  static constexpr double MAXV = 1.7976931348623157e308;
+  static constexpr int EXP_OFF = 1022, EXP_WORDS = 64;  // exponents [-1022, 1024]
+  static constexpr double RANGE = 4611686018427387904.0;  // 2^62
+  __device__ static int exp_of(double a) {
+    return (int)(__double_as_longlong(a) >> 52) - 1022;
+  }
+  __device__ static U bits(double a) { return (U)__double_as_longlong(a); }
+  __device__ static double from(U b) { return __longlong_as_double((long long)b); }
+  __device__ static double ldexp2(double x, int e) { return ldexp(x, e); }
+  static constexpr U NONE = ~0ull;
+};
 
 template <int J, int S>
 __device__ __forceinline__ void flag_footprint(unsigned* flags, int base) {
@@ -510,119 +546,156 @@ __device__ __forceinline__ void flag_footprint(unsigned* flags, int base) {
       }
 }
 
-// The spreading of one task.  REST = false: the task's first class (its only
-// one in the usual case), the non-finite flags, and the number of classes in
-// ncls[task] (1, or 2 when more classes follow).  REST = true: the further
-// classes of the tasks that have them (others return at once), added to the
-// partial.  The two are separate kernels so that the rare multi-pass loop does
-// not cost the usual single pass any registers.
-template <typename T, int J, int TILE, bool CW, int DEG, bool REST>
-__device__ __forceinline__ void spread_task(const cx<T>* __restrict__ in,
+// The spreading of one task.  FIXED: integer accumulation (FP32 always, FP64
+// in deterministic mode).  REST = false (main kernel): tasks that one scale
+// serves; the others append their id to mlist (count in mlist[0], ids after
+// it) and return.  REST = true: a listed task in full.  The two are separate
+// kernels so that the general multi-pass code costs the usual single pass no
+// registers.
+template <typename T, int J, int TILE, bool CW, int DEG, bool FIXED, bool REST>
+__device__ __forceinline__ void spread_task(int64_t task_id, const cx<T>* __restrict__ in,
                                             cx<T>* __restrict__ partials,
                                             const int32_t* __restrict__ perm,
                                             const TileTask* __restrict__ tasks,
-                                            const int32_t* __restrict__ torder,
                                             const float* __restrict__ bound,
-                                            int32_t* __restrict__ ncls_of, const XcdSplit& xs,
-                                            const PointGeom& g, int nb,
-                                            const WeightPoly<T, DEG>& P) {
+                                            int32_t* __restrict__ mlist, const PointGeom& g,
+                                            int nb, const WeightPoly<T, DEG>& P) {
   constexpr int NT_SPREAD = GridCfg<T>::NT_SPREAD;
-  constexpr bool FIXED = sizeof(T) == 4;
+  constexpr bool WIDE = sizeof(T) == 8;  // FP64: one word per component
   constexpr int S = TILE + J - 1;
   constexpr int SS = S * S * S;
   constexpr int R = J - 1;
-  constexpr float FMAX = 3.402823466e38f;
+  using MG = Mag<T>;
+  using U = typename MG::U;
   // FP32: one packed 64-bit word per cell.  FP64: planar accumulators (all
   // real parts, then all imaginary parts), so that a wave's 64-bit atomics
   // spread over every LDS bank instead of half of them.
-  __shared__ double acc[FIXED ? SS : 2 * SS];
-  __shared__ unsigned s_nan[FIXED && !REST ? (SS + 31) / 32 : 1];
-  __shared__ unsigned s_occ[EXP_WORDS];
-  __shared__ int s_ctop[MAX_CLASSES];
-  __shared__ unsigned s_maxbits;
-  __shared__ int s_emin, s_bad, s_ncls;
+  __shared__ double acc[FIXED && !WIDE ? SS : 2 * SS];
+  __shared__ unsigned s_nan[FIXED && REST ? (SS + 31) / 32 : 1];
+  __shared__ unsigned s_occ[FIXED && REST ? MG::EXP_WORDS : 1];
+  __shared__ int s_ctop[FIXED && REST ? MAX_CLASSES : 1];
+  __shared__ U s_maxbits, s_minbits;
+  __shared__ int s_bad, s_ncls;
   unsigned long long* accp = reinterpret_cast<unsigned long long*>(acc);
-  int64_t task_id = xcd_task(blockIdx.x, xs);
-  if (task_id < 0) return;
-  if (torder) task_id = torder[task_id];  // largest tasks of each XCD range first
-  if (REST && ncls_of[task_id] <= 1) return;
   const TileTask tk = tasks[task_id];
   const int b2 = tk.bin % nb, b1 = (tk.bin / nb) % nb, b0 = tk.bin / (nb * nb);
   const int o0 = b0 * TILE, o1 = b1 * TILE, o2 = b2 * TILE;
-  for (int idx = threadIdx.x; idx < (FIXED ? SS : 2 * SS); idx += NT_SPREAD) acc[idx] = 0.0;
-  // magnitude statistics of the task's values (FP32)
-  float vmax = 0.f;
-  int emax = 0, ncls = 1;
+  for (int idx = threadIdx.x; idx < (FIXED && !WIDE ? SS : 2 * SS); idx += NT_SPREAD) acc[idx] = 0.0;
+  // magnitude statistics of the task's values (fixed point)
+  T vmax = 0, scale = 1;
+  double inv = 1.0, bnd = 1.0;
+  int emax = 0, emin = 0, ncls = 1;
   bool bad = false, multi = false;
   if constexpr (FIXED) {
-    if constexpr (!REST)
+    if constexpr (REST)
       for (int idx = threadIdx.x; idx < (SS + 31) / 32; idx += NT_SPREAD) s_nan[idx] = 0u;
     if (threadIdx.x == 0) {
-      s_maxbits = 0u;
-      s_emin = 1 << 20;
+      s_maxbits = 0;
+      s_minbits = MG::NONE;
       s_bad = 0;
     }
-    if (threadIdx.x < EXP_WORDS) s_occ[threadIdx.x] = 0u;
+    if (REST && threadIdx.x < (REST ? MG::EXP_WORDS : 0)) s_occ[threadIdx.x] = 0u;
     __syncthreads();
-    float m = 0.f;
-    int emin = 1 << 20;
-    bool nf = false;
-    // four points per step, so that four dependent load pairs are in flight
-    for (int i0 = threadIdx.x; i0 < tk.count; i0 += 4 * NT_SPREAD) {
-      int id[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int i = i0 + k * NT_SPREAD;
-        id[k] = i < tk.count ? perm[tk.start + i] : -1;
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (id[k] >= 0) {
-          const cx<T> v = in[id[k]];
-          const float ax = fabsf(v.x), ay = fabsf(v.y);
-          if (!(ax <= FMAX) || !(ay <= FMAX)) {
-            nf = true;  // NaN or infinite component
-          } else {
-            const float a = fmaxf(ax, ay);
-            if (a > 0.f) {
-              m = fmaxf(m, a);
-              emin = min(emin, exp_of(a));
-            }
-          }
-        }
-    }
-    // non-negative floats order like their bit patterns
-    atomicMax(&s_maxbits, __float_as_uint(m));
-    atomicMin(&s_emin, emin);
-    if (nf) s_bad = 1;
-    __syncthreads();
-    vmax = __uint_as_float(s_maxbits);
-    bad = s_bad != 0;
-    emax = vmax > 0.f ? exp_of(vmax) : 0;
-    multi = vmax > 0.f && emax - s_emin >= CLASS_BITS;
+    bnd = (double)bound[task_id];
     if constexpr (!REST) {
-      if (threadIdx.x == 0) ncls_of[task_id] = multi ? 2 : 1;
+      // the largest magnitude sets the scale; the smallest non-zero one and
+      // the non-finite values are found on the way through the points, and a
+      // task that needs more than this one scale is then listed instead of
+      // written.  Four points per step
+      T m = 0, ssum = 0;  // (ssum is NaN or infinite if a value is, or if it overflows)
+      for (int i0 = threadIdx.x; i0 < tk.count; i0 += 4 * NT_SPREAD) {
+        int id[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int i = i0 + k * NT_SPREAD;
+          id[k] = i < tk.count ? perm[tk.start + i] : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (id[k] >= 0) {
+            const cx<T> v = in[id[k]];
+            m = fmax(m, fmax(fabs(v.x), fabs(v.y)));  // (NaN operands are ignored)
+            ssum += fabs(v.x) + fabs(v.y);
+          }
+      }
+      if (!(ssum <= (T)MG::MAXV)) s_bad = 1;
+      if constexpr (WIDE)
+        __hip_atomic_fetch_max(&s_maxbits, MG::bits(m), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      else
+        atomicMax(&s_maxbits, MG::bits(m));
+      __syncthreads();
+      vmax = MG::from(s_maxbits);
+      emax = vmax > (T)0 ? MG::exp_of(vmax) : 0;
+      // one scale for the whole task, a normal number, and finite values: else
+      // the task is listed
+      const double sd = vmax > (T)0 && bnd > 0.0 ? (CW ? 0.5 : 1.0) * MG::RANGE / ((double)vmax * bnd) : 1.0;
+      if (s_bad || !(sd >= (sizeof(T) == 4 ? 1.17549435e-38 : 2.2250738585072014e-308) && sd <= (double)MG::MAXV)) {
+        if (threadIdx.x == 0) mlist[1 + atomicAdd(&mlist[0], 1)] = (int32_t)task_id;
+        return;
+      }
+      scale = (T)sd;
     } else {
+      U mx = 0, mn = MG::NONE;  // bits of the largest and smallest non-zero magnitudes
+      bool nf = false;
+      // SC points per step, every load issued unconditionally (lanes past the
+      // end reload the step's first point and ignore it)
+      constexpr int SC = 8;
+      for (int i0 = threadIdx.x; i0 < tk.count; i0 += SC * NT_SPREAD) {
+        int id[SC];
+#pragma unroll
+        for (int k = 0; k < SC; ++k) {
+          const int i = i0 + k * NT_SPREAD;
+          id[k] = perm[tk.start + (i < tk.count ? i : i0)];
+        }
+        cx<T> v[SC];
+#pragma unroll
+        for (int k = 0; k < SC; ++k) v[k] = in[id[k]];
+#pragma unroll
+        for (int k = 0; k < SC; ++k) {
+          const bool ok = i0 + k * NT_SPREAD < tk.count;
+          const T ax = fabs(v[k].x), ay = fabs(v[k].y), a = ax > ay ? ax : ay;
+          const bool fin = ax <= (T)MG::MAXV && ay <= (T)MG::MAXV;  // false for NaN and infinities
+          nf = nf || (ok && !fin);
+          const bool pos = ok && fin && a > (T)0;
+          const U ab = MG::bits(a);  // non-negative values order like their bit patterns
+          mx = pos && ab > mx ? ab : mx;
+          mn = pos && ab < mn ? ab : mn;
+        }
+      }
+      if constexpr (WIDE) {
+        __hip_atomic_fetch_max(&s_maxbits, mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_min(&s_minbits, mn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      } else {
+        atomicMax(&s_maxbits, mx);
+        atomicMin(&s_minbits, mn);
+      }
+      if (nf) s_bad = 1;
+      __syncthreads();
+      vmax = MG::from(s_maxbits);
+      bad = s_bad != 0;
+      emax = vmax > (T)0 ? MG::exp_of(vmax) : 0;
+      emin = vmax > (T)0 ? MG::exp_of(MG::from(s_minbits)) : 0;
+      multi = vmax > (T)0 && emax - emin >= CLASS_BITS;
       // the occupied binades, then the classes: each starts at the highest
       // occupied binade below the previous class and spans CLASS_BITS of them
       for (int i0 = threadIdx.x; i0 < tk.count; i0 += NT_SPREAD) {
         const cx<T> v = in[perm[tk.start + i0]];
-        const float a = fmaxf(fabsf(v.x), fabsf(v.y));
-        if (a > 0.f && a <= FMAX) {
-          const int e = exp_of(a) + EXP_OFF;
+        const T a = fabs(v.x) > fabs(v.y) ? fabs(v.x) : fabs(v.y);
+        if (a > (T)0 && a <= (T)MG::MAXV) {
+          const int e = MG::exp_of(a) + MG::EXP_OFF;
           atomicOr(&s_occ[e >> 5], 1u << (e & 31));
         }
       }
       __syncthreads();
       if (threadIdx.x == 0) {
         int n = 0, e = emax;
-        const int lo = s_emin;
-        while (e >= lo && n < MAX_CLASSES) {
+        while (vmax > (T)0 && e >= emin && n < MAX_CLASSES) {
           s_ctop[n++] = e;
           e -= CLASS_BITS;
-          while (e >= lo && !((s_occ[(e + EXP_OFF) >> 5] >> ((e + EXP_OFF) & 31)) & 1u)) --e;
+          while (e >= emin && !((s_occ[(e + MG::EXP_OFF) >> 5] >> ((e + MG::EXP_OFF) & 31)) & 1u)) --e;
         }
-        s_ncls = n;
+        s_ncls = n > 0 ? n : 1;
+        if (n == 0) s_ctop[0] = 0;
       }
       __syncthreads();
       ncls = s_ncls;
@@ -639,43 +712,44 @@ __device__ __forceinline__ void spread_task(const cx<T>* __restrict__ in,
   const int np = tk.npairs, nunits = tk.count - np;
   cx<T>* dst = partials + task_id * (int64_t)part_stride(TILE, R);
   // no accumulation is needed when every value is zero or non-finite
-  const bool work = !FIXED || vmax > 0.f;
-  for (int cls = REST ? 1 : 0; cls < (REST ? ncls : 1); ++cls) {
-    // the class's scale: v -> ldexp(v, -ctop) f
-    const int ctop = REST ? s_ctop[cls] : emax;
-    float f = 1.f;
-    double inv = 1.0;
-    if constexpr (FIXED) {
-      if (REST && cls > 1) {
+  const bool work = !FIXED || vmax > (T)0;
+  for (int cls = 0; cls < (REST ? ncls : 1); ++cls) {
+    // REST: the class's scale, v -> ldexp(v, -ctop) f, and its decoding
+    int ctop = 0, clo = 0;
+    T f = 1;
+    if constexpr (FIXED && REST) {
+      if (cls > 0) {
         __syncthreads();  // the previous pass's write-out has read the accumulators
-        for (int idx = threadIdx.x; idx < SS; idx += NT_SPREAD) acc[idx] = 0.0;
+        for (int idx = threadIdx.x; idx < (WIDE ? 2 * SS : SS); idx += NT_SPREAD) acc[idx] = 0.0;
         __syncthreads();
       }
-      const double u = cls == 0 ? (double)ldexpf(vmax, -emax) : 1.0;  // class bound / 2^ctop
-      const double bnd = (double)bound[task_id];
-      if (vmax > 0.f && bnd > 0.0) {
-        f = (float)((CW ? 536870912.0 : 1073741824.0) / (u * bnd));  // 2^29 or 2^30
+      ctop = s_ctop[cls];
+      clo = multi ? ctop - CLASS_BITS : -(1 << 20);
+      // class bound / 2^ctop: the exact maximum for the first class
+      const double u = cls == 0 ? (double)MG::ldexp2(vmax, -emax) : 1.0;
+      if (vmax > (T)0 && bnd > 0.0) {
+        f = (T)((CW ? 0.5 : 1.0) * MG::RANGE / (u * bnd));
         inv = ldexp(1.0 / (double)f, ctop);
       }
     }
-    const int clo = multi ? ctop - CLASS_BITS : -(1 << 20);
-    // the scaled value of the class, 0 for values of other classes or
-    // non-finite ones; FP64 values pass unchanged
+    // the scaled value: 0 for values of other classes or non-finite ones
     auto prep = [&](cx<T> v) -> cx<T> {
-      if constexpr (FIXED) {
-        const float ax = fabsf(v.x), ay = fabsf(v.y);
-        if (bad && (!(ax <= FMAX) || !(ay <= FMAX))) return cx<T>{0, 0};
+      if constexpr (!FIXED) {
+        return v;
+      } else if constexpr (!REST) {
+        return cx<T>{v.x * scale, v.y * scale};
+      } else {
+        const T ax = fabs(v.x), ay = fabs(v.y);
+        if (!(ax <= (T)MG::MAXV) || !(ay <= (T)MG::MAXV)) return cx<T>{0, 0};
         if (multi) {
-          const float a = fmaxf(ax, ay);
-          const int e = a > 0.f ? exp_of(a) : clo;
+          const T a = ax > ay ? ax : ay;
+          const int e = a > (T)0 ? MG::exp_of(a) : clo;
           if (e > ctop || e <= clo) return cx<T>{0, 0};
         }
-        return cx<T>{ldexpf(v.x, -ctop) * f, ldexpf(v.y, -ctop) * f};
-      } else {
-        return v;
+        return cx<T>{MG::ldexp2(v.x, -ctop) * f, MG::ldexp2(v.y, -ctop) * f};
       }
     };
-    auto nonfinite = [](cx<T> v) { return !(fabsf((float)v.x) <= FMAX) || !(fabsf((float)v.y) <= FMAX); };
+    auto nonfinite = [](cx<T> v) { return !(fabs(v.x) <= (T)MG::MAXV) || !(fabs(v.y) <= (T)MG::MAXV); };
     PtRaw nxt, nxt2;
     cx<T> vnxt = {0, 0}, vnxt2 = {0, 0};
     auto fetch_unit = [&](int u) {  // one unit ahead (its second point if paired)
@@ -688,8 +762,11 @@ __device__ __forceinline__ void spread_task(const cx<T>* __restrict__ in,
         vnxt2 = in[nxt2.p];
       }
     };
-    if ((work || bad) && (int)threadIdx.x < nunits) fetch_unit(threadIdx.x);
-    for (int u = threadIdx.x; (work || bad) && u < nunits; u += NT_SPREAD) {
+    const bool go = work || (REST && bad);
+    T tmn = (T)INFINITY;  // main kernel: the smallest non-zero magnitude
+    cx<T> vs1 = {0, 0}, vs2 = {0, 0};
+    if (go && (int)threadIdx.x < nunits) fetch_unit(threadIdx.x);
+    for (int u = threadIdx.x; go && u < nunits; u += NT_SPREAD) {
       PtRaw cur = nxt, cur2 = nxt2;
       cx<T> v = vnxt, v2 = vnxt2;
       const bool pair = u < np;
@@ -698,13 +775,24 @@ __device__ __forceinline__ void spread_task(const cx<T>* __restrict__ in,
         cur2 = fetch_point(g, perm, tk.start + 2 * u + 1);
         v2 = in[cur2.p];
       }
-      const bool bad1 = FIXED && !REST && bad && nonfinite(v);
-      const bool bad2 = FIXED && !REST && bad && pair && nonfinite(v2);
+      // (the flags are set once, in the first class's pass)
+      const bool bad1 = FIXED && REST && bad && cls == 0 && nonfinite(v);
+      const bool bad2 = FIXED && REST && bad && cls == 0 && pair && nonfinite(v2);
+      if constexpr (FIXED && !REST) {
+        // the smallest non-zero magnitude and the non-finite values, from the
+        // scaled values (the second point of a unit is zero when there is
+        // none); taken here rather than on arrival, where waiting for the
+        // prefetched values would expose their latency
+        vs1 = v;
+        vs2 = v2;
+      }
       v = prep(v);
       v2 = prep(v2);
-      const bool nz1 = v.x != (T)0 || v.y != (T)0, nz2 = pair && (v2.x != (T)0 || v2.y != (T)0);
-      // nothing to add (zero values, or values of other classes) and nothing to flag
-      if (!nz1 && !nz2 && !bad1 && !bad2) continue;
+      if constexpr (FIXED && REST) {
+        // nothing to add (values of other classes) and nothing to flag
+        const bool nz = v.x != (T)0 || v.y != (T)0 || (pair && (v2.x != (T)0 || v2.y != (T)0));
+        if (!nz && !bad1 && !bad2) continue;
+      }
       int first[3], first2[3] = {0, 0, 0};
       double frac[3], frac2[3] = {0.0, 0.0, 0.0};
       point_taps<sizeof(T) == 4>(g, cur, J, first, frac);
@@ -722,48 +810,81 @@ __device__ __forceinline__ void spread_task(const cx<T>* __restrict__ in,
         point_taps<sizeof(T) == 4>(g, cur2, J, first2, frac2);
         same = first2[0] == first[0] && first2[1] == first[1] && first2[2] == first[2];
       }
-      const int m0 = first2[0] - o0, m1 = first2[1] - o1, m2 = first2[2] - o2;
-      const bool in2 = pair && (unsigned)m0 < (unsigned)TILE && (unsigned)m1 < (unsigned)TILE &&
-                       (unsigned)m2 < (unsigned)TILE;
-      if constexpr (FIXED && !REST) {
+      if constexpr (FIXED && REST) {
+        const int m0 = first2[0] - o0, m1 = first2[1] - o1, m2 = first2[2] - o2;
         if (bad1 && in1) flag_footprint<J, S>(s_nan, (l0 * S + l1) * S + l2);
-        if (bad2 && in2) flag_footprint<J, S>(s_nan, (m0 * S + m1) * S + m2);
+        if (bad2 && (unsigned)m0 < (unsigned)TILE && (unsigned)m1 < (unsigned)TILE &&
+            (unsigned)m2 < (unsigned)TILE)
+          flag_footprint<J, S>(s_nan, (m0 * S + m1) * S + m2);
+      }
+      if constexpr (FIXED && !REST) {
+        // (the values are finite here; zeros are left out by mapping them to +inf)
+        const T a1 = fmax(fabs(vs1.x), fabs(vs1.y)), a2 = fmax(fabs(vs2.x), fabs(vs2.y));
+        tmn = fmin(tmn, fmin(a1 > (T)0 ? a1 : (T)INFINITY, a2 > (T)0 ? a2 : (T)INFINITY));
       }
       if constexpr (PAIRED) {
         // (a single point, or a pair whose first cells differ, adds a zero here)
+        T x0r[J], x0i[J], x1r[J], x1i[J], x2r[J], x2i[J];
         const bool both = pair && same;
-        if (in1 && (nz1 || (both && nz2))) {
-          T x0r[J], x0i[J], x1r[J], x1i[J], x2r[J], x2i[J];
-          axis_weights<T, J, DEG, CW>(P, both ? frac2[0] : frac[0], x0r, x0i);
-          axis_weights<T, J, DEG, CW>(P, both ? frac2[1] : frac[1], x1r, x1i);
-          axis_weights<T, J, DEG, CW>(P, both ? frac2[2] : frac[2], x2r, x2i);
-          const cx<T> vq = both ? v2 : cx<T>{0, 0};
-          spread_pair<T, J, S, SS>(accp, acc, v, vq, (l0 * S + l1) * S + l2, w0r, w1r, w2r, x0r,
-                                   x1r, x2r);
-        }
+        axis_weights<T, J, DEG, CW>(P, both ? frac2[0] : frac[0], x0r, x0i);
+        axis_weights<T, J, DEG, CW>(P, both ? frac2[1] : frac[1], x1r, x1i);
+        axis_weights<T, J, DEG, CW>(P, both ? frac2[2] : frac[2], x2r, x2i);
+        const cx<T> vq = both ? v2 : cx<T>{0, 0};
+        if (in1)
+          spread_pair<T, J, S, SS, FIXED>(accp, acc, v, vq, (l0 * S + l1) * S + l2, w0r, w1r, w2r,
+                                          x0r, x1r, x2r);
       } else {
-        if (in1 && nz1)
-          spread_one<T, J, S, SS, CW>(accp, acc, v, (l0 * S + l1) * S + l2, w0r, w0i, w1r, w1i,
-                                      w2r, w2i);
+        if (in1)
+          spread_one<T, J, S, SS, CW, FIXED>(accp, acc, v, (l0 * S + l1) * S + l2, w0r, w0i, w1r,
+                                             w1i, w2r, w2i);
       }
-      if (pair && (!PAIRED || !same) && in2 && nz2) {
+      if (pair && (!PAIRED || !same)) {
         // the second point on its own (or first cells that differ in the
         // device's rounding of a tie)
-        axis_weights<T, J, DEG, CW>(P, frac2[0], w0r, w0i);
-        axis_weights<T, J, DEG, CW>(P, frac2[1], w1r, w1i);
-        axis_weights<T, J, DEG, CW>(P, frac2[2], w2r, w2i);
-        spread_one<T, J, S, SS, CW>(accp, acc, v2, (m0 * S + m1) * S + m2, w0r, w0i, w1r, w1i,
-                                    w2r, w2i);
+        const int m0 = first2[0] - o0, m1 = first2[1] - o1, m2 = first2[2] - o2;
+        if ((unsigned)m0 < (unsigned)TILE && (unsigned)m1 < (unsigned)TILE &&
+            (unsigned)m2 < (unsigned)TILE) {
+          axis_weights<T, J, DEG, CW>(P, frac2[0], w0r, w0i);
+          axis_weights<T, J, DEG, CW>(P, frac2[1], w1r, w1i);
+          axis_weights<T, J, DEG, CW>(P, frac2[2], w2r, w2i);
+          spread_one<T, J, S, SS, CW, FIXED>(accp, acc, v2, (m0 * S + m1) * S + m2, w0r, w0i, w1r,
+                                             w1i, w2r, w2i);
+        }
+      }
+    }
+    if constexpr (FIXED && !REST) {
+      // a task that needs more than one scale goes to the general kernel
+      const U tmb = tmn <= (T)MG::MAXV ? MG::bits(tmn) : MG::NONE;
+      if constexpr (WIDE)
+        __hip_atomic_fetch_min(&s_minbits, tmb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      else
+        atomicMin(&s_minbits, tmb);
+      __syncthreads();
+      const U mnb = s_minbits;
+      const bool wide_range = mnb != MG::NONE && vmax > (T)0 && emax - MG::exp_of(MG::from(mnb)) >= CLASS_BITS;
+      if (wide_range) {
+        if (threadIdx.x == 0) mlist[1 + atomicAdd(&mlist[0], 1)] = (int32_t)task_id;
+        return;
       }
     }
     __syncthreads();
     // write the partial block by block (consecutive threads, consecutive
     // addresses), see part_offset; further classes add to what the first wrote
-    auto decode = [&](unsigned long long w, int cell) {  // the two sums of a packed word
-      const long long lo = (long long)(int)(unsigned int)(w & 0xffffffffull);
-      const long long hi = (long long)(w - (unsigned long long)lo) >> 32;
-      cx<T> r = cx<T>{(T)((double)hi * inv), (T)((double)lo * inv)};
-      if constexpr (!REST)
+    const bool add = REST && cls > 0;
+    if constexpr (FIXED && !REST) inv = 1.0 / (double)scale;  // (not live across the loop)
+    auto decode = [&](int cell) -> cx<T> {  // the two sums of a cell
+      cx<T> r;
+      if constexpr (!FIXED) {
+        r = cx<T>{(T)acc[cell], (T)acc[SS + cell]};
+      } else if constexpr (WIDE) {
+        r = cx<T>{(T)((double)(long long)accp[cell] * inv), (T)((double)(long long)accp[SS + cell] * inv)};
+      } else {
+        const unsigned long long w = accp[cell];
+        const long long lo = (long long)(int)(unsigned int)(w & 0xffffffffull);
+        const long long hi = (long long)(w - (unsigned long long)lo) >> 32;
+        r = cx<T>{(T)((double)hi * inv), (T)((double)lo * inv)};
+      }
+      if constexpr (FIXED && REST)
         if (bad && ((s_nan[cell >> 5] >> (cell & 31)) & 1u)) r = cx<T>{(T)NAN, (T)NAN};
       return r;
     };
@@ -772,7 +893,7 @@ __device__ __forceinline__ void spread_task(const cx<T>* __restrict__ in,
       const int d0 = (delta >> 2) & 1, d1 = (delta >> 1) & 1, d2 = delta & 1;
       const int e1 = part_ext(d1, TILE, R), e2 = part_ext(d2, TILE, R);
       const int n = part_size(delta, TILE, R), base = part_base(delta, TILE, R);
-      if constexpr (FIXED) {
+      if constexpr (FIXED && !WIDE) {
         // blocks whose rows have an even length (and an even base): two cells
         // of a row per lane, one 16-byte store
         if ((e2 & 1) == 0) {
@@ -784,10 +905,10 @@ __device__ __forceinline__ void spread_task(const cx<T>* __restrict__ in,
               const int idx = 2 * j;
               const int r2 = idx % e2, r1 = (idx / e2) % e1, r0 = idx / (e1 * e2);
               const int cell = ((r0 + d0 * TILE) * S + (r1 + d1 * TILE)) * S + (r2 + d2 * TILE);
-              const cx<T> a = decode(accp[cell], cell), b = decode(accp[cell + 1], cell + 1);
+              const cx<T> a = decode(cell), b = decode(cell + 1);
               float4 o = make_float4(a.x, a.y, b.x, b.y);
               float4* q = reinterpret_cast<float4*>(dst + base) + j;
-              if constexpr (REST) {
+              if (add) {
                 const float4 p = *q;
                 o = make_float4(p.x + o.x, p.y + o.y, p.z + o.z, p.w + o.w);
               }
@@ -800,39 +921,42 @@ __device__ __forceinline__ void spread_task(const cx<T>* __restrict__ in,
       for (int idx = threadIdx.x; idx < n; idx += NT_SPREAD) {
         const int r2 = idx % e2, r1 = (idx / e2) % e1, r0 = idx / (e1 * e2);
         const int cell = ((r0 + d0 * TILE) * S + (r1 + d1 * TILE)) * S + (r2 + d2 * TILE);
-        cx<T> v;
-        if constexpr (FIXED) {
-          v = decode(accp[cell], cell);
-          if constexpr (REST) v = cadd(v, dst[base + idx]);
-        } else {
-          v = cx<T>{(T)acc[cell], (T)acc[SS + cell]};
-        }
+        cx<T> v = decode(cell);
+        if (add) v = cadd(v, dst[base + idx]);
         dst[base + idx] = v;
       }
     }
   }
 }
 
-template <typename T, int J, int TILE, bool CW, int DEG>
+template <typename T, int J, int TILE, bool CW, int DEG, bool FIXED>
 __global__ __launch_bounds__(GridCfg<T>::NT_SPREAD)
 __attribute__((amdgpu_waves_per_eu(GridCfg<T>::SPREAD_WAVES))) void k_spread(
     const cx<T>* __restrict__ in, cx<T>* __restrict__ partials, const int32_t* __restrict__ perm,
     const TileTask* __restrict__ tasks, const int32_t* __restrict__ torder,
-    const float* __restrict__ bound, int32_t* __restrict__ ncls_of, XcdSplit xs, PointGeom g,
+    const float* __restrict__ bound, int32_t* __restrict__ mlist, XcdSplit xs, PointGeom g,
     int nb, WeightPoly<T, DEG> P) {
-  spread_task<T, J, TILE, CW, DEG, false>(in, partials, perm, tasks, torder, bound, ncls_of, xs,
-                                          g, nb, P);
+  int64_t task_id = xcd_task(blockIdx.x, xs);
+  if (task_id < 0) return;
+  if (torder) task_id = torder[task_id];  // largest tasks of each XCD range first
+  spread_task<T, J, TILE, CW, DEG, FIXED, false>(task_id, in, partials, perm, tasks, bound, mlist,
+                                                 g, nb, P);
 }
 
-// FP32: the further magnitude classes of the tasks that have them
+// Fixed point: the listed tasks in full (a few blocks walk the list, so that
+// the usual empty list costs one small launch)
+constexpr int NB_REST = 512;
 template <typename T, int J, int TILE, bool CW, int DEG>
 __global__ __launch_bounds__(GridCfg<T>::NT_SPREAD) void k_spread_rest(
     const cx<T>* __restrict__ in, cx<T>* __restrict__ partials, const int32_t* __restrict__ perm,
-    const TileTask* __restrict__ tasks, const int32_t* __restrict__ torder,
-    const float* __restrict__ bound, int32_t* __restrict__ ncls_of, XcdSplit xs, PointGeom g,
-    int nb, WeightPoly<T, DEG> P) {
-  spread_task<T, J, TILE, CW, DEG, true>(in, partials, perm, tasks, torder, bound, ncls_of, xs,
-                                         g, nb, P);
+    const TileTask* __restrict__ tasks, const float* __restrict__ bound,
+    int32_t* __restrict__ mlist, PointGeom g, int nb, WeightPoly<T, DEG> P) {
+  const int count = mlist[0];
+  for (int i = blockIdx.x; i < count; i += gridDim.x) {
+    spread_task<T, J, TILE, CW, DEG, true, true>(mlist[1 + i], in, partials, perm, tasks, bound,
+                                                 mlist, g, nb, P);
+    __syncthreads();  // the next task reuses the LDS
+  }
 }
 
 // Plan-time bound for the FP32 spreading scale: per task, the largest over
@@ -907,7 +1031,10 @@ __global__ __launch_bounds__(NT_BOUND) void k_spread_bound(float* __restrict__ b
 template <typename T, int TILE>
 __global__ __launch_bounds__(TILE * TILE * TILE < 1024 ? TILE * TILE * TILE : 1024) void k_merge(
     const cx<T>* __restrict__ partials, const int32_t* __restrict__ bin_tasks,
-    const int32_t* __restrict__ order, cx<T>* __restrict__ grid, int nb, int K, int R, double r2) {
+    const int32_t* __restrict__ order, cx<T>* __restrict__ grid, int nb, int K, int R, double r2,
+    int32_t* __restrict__ mlist) {
+  // the spreading's list of multi-class tasks has been consumed: empty it
+  if (mlist && blockIdx.x == 0 && threadIdx.x == 0) mlist[0] = 0;
   constexpr int TT = TILE * TILE * TILE;
   constexpr int NTM = TT < 1024 ? TT : 1024;
   constexpr int PER = TT / NTM;
@@ -982,7 +1109,10 @@ __global__ __launch_bounds__(1024) void k_merge_pairs(const cx<float>* __restric
                                                       const int32_t* __restrict__ bin_tasks,
                                                       const int32_t* __restrict__ order,
                                                       cx<float>* __restrict__ grid, int nb, int K,
-                                                      int R, double r2) {
+                                                      int R, double r2,
+                                                      int32_t* __restrict__ mlist) {
+  // the spreading's list of multi-class tasks has been consumed: empty it
+  if (mlist && blockIdx.x == 0 && threadIdx.x == 0) mlist[0] = 0;
   constexpr int TTC = TILE * TILE * TILE / C;
   constexpr int NTM = TTC < 1024 ? TTC : 1024;
   constexpr int PER = TTC / NTM;
@@ -1090,27 +1220,32 @@ constexpr bool tile_fits() {  // the spread's FP64 halo tile must fit in LDS
   return (TILE + J - 1) * (TILE + J - 1) * (TILE + J - 1) * 16 <= 160 * 1024 && J - 1 <= TILE;
 }
 
-enum Op { OP_INTERP = 0, OP_SPREAD = 1, OP_BOUND = 2 };
+// OP_SPREAD_DET: FP64 spreading in fixed point (deterministic mode); the FP32
+// spreading is always fixed point
+enum Op { OP_INTERP = 0, OP_SPREAD = 1, OP_BOUND = 2, OP_SPREAD_DET = 3 };
 
 template <typename T, int J, int TILE, bool CW, int OP>
 hipError_t launch_one(const nufftct_plan& p, const void* src, void* dst, hipStream_t st) {
-  if constexpr (!tile_fits<T, J, TILE>() || (OP == OP_BOUND && sizeof(T) != 4)) {
+  if constexpr (!tile_fits<T, J, TILE>() || (OP == OP_SPREAD_DET && sizeof(T) == 4)) {
     return hipErrorInvalidValue;
   } else {
     constexpr int DEG = PolyOf<T>::DEG;
     const auto& P = PolyOf<T>::get(p);
     const dim3 grd((unsigned)((int64_t)p.xsplit.max_len * NUFFTCT_NUM_XCD));
     const PointGeom g = p.geom();
-    if constexpr (OP == OP_SPREAD) {
-      hipLaunchKernelGGL((k_spread<T, J, TILE, CW, DEG>), grd, dim3(GridCfg<T>::NT_SPREAD), 0, st,
-                         (const cx<T>*)src, (cx<T>*)p.d_partials, p.d_perm_s, p.d_tasks,
-                         p.d_spread_order, p.d_bound, p.d_ncls, p.xsplit, g, p.nb, P);
-      if constexpr (sizeof(T) == 4) {
+    if constexpr (OP == OP_SPREAD || OP == OP_SPREAD_DET) {
+      constexpr bool FX = sizeof(T) == 4 || OP == OP_SPREAD_DET;
+      hipLaunchKernelGGL((k_spread<T, J, TILE, CW, DEG, FX>), grd, dim3(GridCfg<T>::NT_SPREAD), 0,
+                         st, (const cx<T>*)src, (cx<T>*)p.d_partials, p.d_perm_s, p.d_tasks,
+                         p.d_spread_order, p.d_bound, p.d_multi, p.xsplit, g, p.nb, P);
+      if constexpr (FX) {
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_spread_rest<T, J, TILE, CW, DEG>), grd, dim3(GridCfg<T>::NT_SPREAD),
-                           0, st, (const cx<T>*)src, (cx<T>*)p.d_partials, p.d_perm_s, p.d_tasks,
-                           p.d_spread_order, p.d_bound, p.d_ncls, p.xsplit, g, p.nb, P);
+        const unsigned nbr = (unsigned)std::min<int64_t>(p.ntasks, NB_REST);
+        hipLaunchKernelGGL((k_spread_rest<T, J, TILE, CW, DEG>), dim3(nbr),
+                           dim3(GridCfg<T>::NT_SPREAD), 0, st, (const cx<T>*)src,
+                           (cx<T>*)p.d_partials, p.d_perm_s, p.d_tasks, p.d_bound, p.d_multi, g,
+                           p.nb, P);
       }
     } else if constexpr (OP == OP_BOUND) {
       hipLaunchKernelGGL((k_spread_bound<T, J, TILE, CW, DEG>), grd, dim3(NT_BOUND), 0, st,
@@ -1150,6 +1285,7 @@ hipError_t by_j(const nufftct_plan& p, const void* src, void* dst, hipStream_t s
 template <typename T, int OP>
 hipError_t run(const nufftct_plan& p, const void* src, void* dst, hipStream_t st) {
   if (p.ntasks == 0) return hipSuccess;
+  if constexpr (OP == OP_SPREAD_DET && sizeof(T) == 4) return run<T, OP_SPREAD>(p, src, dst, st);
   if (p.kernel == NUFFTCT_KERNEL_MINMAX_KB) return by_j<T, true, OP>(p, src, dst, st);
   return by_j<T, false, OP>(p, src, dst, st);
 }
@@ -1162,15 +1298,18 @@ hipError_t merge(const nufftct_plan& p, void* grid, hipStream_t st, bool prune) 
   if (p.tile == 16 && sizeof(T) == 4) {
     hipLaunchKernelGGL((k_merge_pairs<16, 2>), grd, dim3(1024), 0, st,
                        (const cx<float>*)p.d_partials,
-                       p.d_bin_tasks, p.d_merge_order, (cx<float>*)grid, p.nb, (int)p.K, R, r2);
+                       p.d_bin_tasks, p.d_merge_order, (cx<float>*)grid, p.nb, (int)p.K, R, r2,
+                       p.d_multi);
     return hipGetLastError();
   }
   if (p.tile == 16)
     hipLaunchKernelGGL((k_merge<T, 16>), grd, dim3(1024), 0, st, (const cx<T>*)p.d_partials,
-                       p.d_bin_tasks, p.d_merge_order, (cx<T>*)grid, p.nb, (int)p.K, R, r2);
+                       p.d_bin_tasks, p.d_merge_order, (cx<T>*)grid, p.nb, (int)p.K, R, r2,
+                       p.d_multi);
   else if (p.tile == 8)
     hipLaunchKernelGGL((k_merge<T, 8>), grd, dim3(512), 0, st, (const cx<T>*)p.d_partials,
-                       p.d_bin_tasks, p.d_merge_order, (cx<T>*)grid, p.nb, (int)p.K, R, r2);
+                       p.d_bin_tasks, p.d_merge_order, (cx<T>*)grid, p.nb, (int)p.K, R, r2,
+                       p.d_multi);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -1186,8 +1325,9 @@ hipError_t merge(const nufftct_plan& p, void* grid, hipStream_t st, bool prune) 
   }                                                                                         \
   template <>                                                                               \
   hipError_t launch_spread<T>(const nufftct_plan& p, const void* in, void* grid,            \
-                              hipStream_t s) {                                              \
-    return kgrid::run<T, kgrid::OP_SPREAD>(p, in, grid, s);                                 \
+                              hipStream_t s, bool det) {                                    \
+    return det ? kgrid::run<T, kgrid::OP_SPREAD_DET>(p, in, grid, s)                        \
+               : kgrid::run<T, kgrid::OP_SPREAD>(p, in, grid, s);                           \
   }                                                                                         \
   template <>                                                                               \
   hipError_t launch_spread_bound<T>(const nufftct_plan& p, hipStream_t s) {                 \

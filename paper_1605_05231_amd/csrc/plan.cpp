@@ -299,7 +299,7 @@ static void free_plan(nufftct_plan* p) {
   hipFree(p->d_spread_order);
   hipFree(p->d_partials);
   hipFree(p->d_bound);
-  hipFree(p->d_ncls);
+  hipFree(p->d_multi);
   hipFree(p->d_line_w);
   hipFree(p->d_grid);
   hipFree(p->d_tmp);
@@ -656,16 +656,20 @@ static int create(nufftct_plan** out, int64_t N, int64_t K, int J, int kernel, d
       return fail(NUFFTCT_ENOMEM, "workspace of %zu bytes: %s", p->tmp_bytes, hipGetErrorString(e));
     }
   }
-  // FP32 spreading: per-task bounds that set its fixed-point scale
-  if (precision == NUFFTCT_FP32) {
+  // per-task bounds that set the fixed-point spreading's scale (FP32 always,
+  // FP64 in deterministic mode)
+  {
     const size_t bbytes = (size_t)std::max<int64_t>(p->ntasks, 1) * sizeof(float);
     hipError_t e = hipMalloc(&p->d_bound, bbytes);
-    if (e == hipSuccess) e = hipMalloc(&p->d_ncls, (size_t)std::max<int64_t>(p->ntasks, 1) * sizeof(int32_t));
+    const size_t mbytes = (size_t)(std::max<int64_t>(p->ntasks, 1) + 1) * sizeof(int32_t);
+    if (e == hipSuccess) e = hipMalloc(&p->d_multi, mbytes);
+    if (e == hipSuccess) e = hipMemsetAsync(p->d_multi, 0, mbytes, st);  // the empty list
     if (e != hipSuccess) {
       free_plan(p);
       return fail(NUFFTCT_ENOMEM, "spread bounds of %zu bytes: %s", bbytes, hipGetErrorString(e));
     }
-    e = launch_spread_bound<float>(*p, st);
+    e = precision == NUFFTCT_FP32 ? launch_spread_bound<float>(*p, st)
+                                  : launch_spread_bound<double>(*p, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
       free_plan(p);
@@ -738,7 +742,7 @@ static hipError_t run_stage(nufftct_plan* p, int stage, const void* in, void* ou
     case NUFFTCT_STAGE_SPREAD: {
       // halo partials per task, then the owner-computes merge writes every
       // grid cell (timed on its own slot)
-      e = launch_spread<T>(*p, in, out, st);
+      e = launch_spread<T>(*p, in, out, st, (flags & NUFFTCT_DETERMINISTIC) != 0);
       tm.done();
       StageTimer tr(p, st, NUFFTCT_TIMING_MERGE);
       if (e == hipSuccess) e = launch_merge<T>(*p, out, st, prune);
@@ -760,7 +764,8 @@ static int check_call(nufftct_plan* p, const void* a, void* b, int flags) {
   if (!p) return fail(NUFFTCT_EINVAL, "plan is NULL");
   if (!a || !b) return fail(NUFFTCT_EINVAL, "data pointer is NULL");
   if (a == b) return fail(NUFFTCT_EINVAL, "input and output must not alias");
-  if (flags & ~NUFFTCT_DERIV_RADIAL) return fail(NUFFTCT_EINVAL, "unknown flags %d", flags);
+  if (flags & ~(NUFFTCT_DERIV_RADIAL | NUFFTCT_DETERMINISTIC))
+    return fail(NUFFTCT_EINVAL, "unknown flags %d", flags);
   if ((flags & NUFFTCT_DERIV) && !(flags & NUFFTCT_RADIAL))
     return fail(NUFFTCT_EINVAL, "NUFFTCT_DERIV requires NUFFTCT_RADIAL");
   if ((flags & NUFFTCT_RADIAL) && p->n_r == 0)
@@ -842,15 +847,45 @@ int nufftct_autotune_radial(int64_t N, int64_t K, int J, int kernel, double beta
     hipFree(vol);
     return fail(NUFFTCT_ENOMEM, "autotune buffers");
   }
-  // any non-zero pattern: the run time does not depend on the values
+  // Inputs: pseudo-random values in [-1, 1) for the volume and, separately,
+  // for the adjoint's input.  The spreading's cost depends on the spread of
+  // magnitudes within a task (tasks spanning many binades take an extra
+  // pass); random data keep that spread ordinary, where a constant volume, or
+  // the forward output of one, would not.
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  hipError_t he = hipMemsetAsync(vol, 0x3c, (size_t)N * N * N * cxb, st);
+  void* din = nullptr;
+  hipError_t he = hipMalloc(&din, (size_t)M * cxb);
+  {
+    uint64_t st64 = 0x9e3779b97f4a7c15ull;
+    auto next = [&]() {  // xorshift64*
+      st64 ^= st64 >> 12;
+      st64 ^= st64 << 25;
+      st64 ^= st64 >> 27;
+      return (double)((st64 * 2685821657736338717ull) >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+    };
+    auto fill = [&](void* dst, size_t ncomplex) {
+      const size_t nval = 2 * ncomplex;
+      if (precision == NUFFTCT_FP64) {
+        std::vector<double> h(nval);
+        for (auto& v : h) v = next();
+        hipError_t e = hipMemcpyAsync(dst, h.data(), nval * sizeof(double), hipMemcpyHostToDevice, st);
+        return e == hipSuccess ? hipStreamSynchronize(st) : e;  // before h goes out of scope
+      }
+      std::vector<float> h(nval);
+      for (auto& v : h) v = (float)next();
+      hipError_t e = hipMemcpyAsync(dst, h.data(), nval * sizeof(float), hipMemcpyHostToDevice, st);
+      return e == hipSuccess ? hipStreamSynchronize(st) : e;
+    };
+    if (he == hipSuccess) he = fill(vol, (size_t)N * N * N);
+    if (he == hipSuccess) he = fill(din, (size_t)M);
+  }
   if (he == hipSuccess) he = hipEventCreate(&e0);
   if (he == hipSuccess) he = hipEventCreate(&e1);
   if (he != hipSuccess) {
     if (e0) hipEventDestroy(e0);
     hipFree(vol);
     hipFree(out);
+    hipFree(din);
     return fail(NUFFTCT_EHIP, "autotune set-up: %s", hipGetErrorString(he));
   }
   const int tiles[2] = {16, 8};
@@ -867,11 +902,11 @@ int nufftct_autotune_radial(int64_t N, int64_t K, int J, int kernel, double beta
         continue;
       }
       int rc = nufftct_forward(p, vol, out, flags, stream);
-      if (!rc) rc = nufftct_adjoint(p, out, vol, flags, stream);
+      if (!rc) rc = nufftct_adjoint(p, din, vol, flags, stream);
       if (!rc && hipEventRecord(e0, st) != hipSuccess) rc = NUFFTCT_EHIP;
       for (int r = 0; r < 2 && !rc; ++r) {
         rc = nufftct_forward(p, vol, out, flags, stream);
-        if (!rc) rc = nufftct_adjoint(p, out, vol, flags, stream);
+        if (!rc) rc = nufftct_adjoint(p, din, vol, flags, stream);
       }
       if (!rc && hipEventRecord(e1, st) != hipSuccess) rc = NUFFTCT_EHIP;
       float ms = 0;
@@ -887,6 +922,7 @@ int nufftct_autotune_radial(int64_t N, int64_t K, int J, int kernel, double beta
         hipEventDestroy(e1);
         hipFree(vol);
         hipFree(out);
+        hipFree(din);
         return fail(NUFFTCT_EHIP, "autotune candidate failed: %s", hipGetErrorString(se));
       }
     }
@@ -894,6 +930,7 @@ int nufftct_autotune_radial(int64_t N, int64_t K, int J, int kernel, double beta
   hipEventDestroy(e1);
   hipFree(vol);
   hipFree(out);
+  hipFree(din);
   if (bv.tile == 0) return fail(NUFFTCT_EHIP, "no autotune candidate ran");
   tune_store(TuneKey{N, K, J, kernel, precision, n_lines, n_r, M, geom_hash(dirs, 3 * n_lines)}, bv);
   if (best_tile) *best_tile = bv.tile;

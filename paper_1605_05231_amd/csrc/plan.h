@@ -73,8 +73,8 @@ struct nufftct_plan {
   int32_t* d_merge_order = nullptr;  // nb^3 tiles in merge dispatch order, heaviest first
   int32_t* d_spread_order = nullptr; // ntasks: spreading dispatch order (per XCD range, largest first)
   void* d_partials = nullptr;      // per task, its spread halo tile (S^3 complex)
-  float* d_bound = nullptr;        // FP32: per task, max over halo cells of sum |w|
-  int32_t* d_ncls = nullptr;       // FP32: per task, 1 or 2 (further magnitude classes follow)
+  float* d_bound = nullptr;        // per task, max over halo cells of sum |w| (fixed-point scale)
+  int32_t* d_multi = nullptr;      // count, then the ids of the tasks the general spreading kernel takes
   double* d_line_w = nullptr;      // radial plans: per-line reconstruction weights (optional)
   void* d_grid = nullptr;       // K^3 complex workspace
   void* d_tmp = nullptr;        // M complex workspace
@@ -124,10 +124,12 @@ hipError_t launch_radial(const nufftct_plan& p, const void* in, void* out, bool 
 // interpolation / spreading (k_grid.hip)
 template <typename T>
 hipError_t launch_interp(const nufftct_plan& p, const void* grid, void* out, hipStream_t s);
+// det: FP64 plans spread in fixed point (bitwise reproducible); FP32 always does
 template <typename T>
-hipError_t launch_spread(const nufftct_plan& p, const void* in, void* grid, hipStream_t s);
-// FP32 plans, at creation: per task, the bound on the summed weight
-// magnitudes at any halo cell that sets the spreading's fixed-point scale
+hipError_t launch_spread(const nufftct_plan& p, const void* in, void* grid, hipStream_t s,
+                         bool det = false);
+// at plan creation: per task, the bound on the summed weight magnitudes at
+// any halo cell that sets the spreading's fixed-point scale
 template <typename T>
 hipError_t launch_spread_bound(const nufftct_plan& p, hipStream_t s);
 hipError_t launch_zero(void* ptr, size_t bytes, hipStream_t s);

@@ -193,15 +193,19 @@ def test_forward_deterministic(S):
     assert torch.equal(a, b)
 
 
-def test_adjoint_deterministic_fp32(S):
-    """The FP32 spreading sums integers, so the adjoint is bitwise reproducible."""
+def test_adjoint_deterministic(S):
+    """Bitwise reproducible adjoints: the FP32 spreading always sums integers;
+    the FP64 form does in deterministic mode, which must also meet the FP64
+    bar against the oracle."""
     import torch
-    if S.prec != "f32":
-        pytest.skip("FP32 path")
     yd = to_dev(S.y, _torch_dtype(S.prec))
-    a = S.plan.adjoint(yd)
+    det = S.prec == "f64"
+    a = S.plan.adjoint(yd, deterministic=det)
     for _ in range(3):
-        assert torch.equal(a, S.plan.adjoint(yd))
+        assert torch.equal(a, S.plan.adjoint(yd, deterministic=det))
+    if det:
+        want = projector.adjoint(S.y, S.dirs, S.n_r, S.prm)
+        check(f"deterministic adj {S.name} f64", to_host(a), want, f64_tol(S, TOL["f64"]))
 
 
 # ---------------------------------------------------------------------------

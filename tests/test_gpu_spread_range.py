@@ -63,10 +63,10 @@ def geo():
     return {"dirs": dirs, "prm": prm, "om": om, "p32": p32, "p64": p64, "bmax": bmax}
 
 
-def _spread(plan, y, dtype):
+def _spread(plan, y, dtype, deterministic=False):
     import torch
     g = torch.empty(K ** 3, dtype=dtype, device="cuda")
-    plan.stage(4, to_dev(y, dtype), g)  # STAGE_SPREAD: centred grid
+    plan.stage(4, to_dev(y, dtype), g, deterministic=deterministic)  # STAGE_SPREAD: centred grid
     return np.fft.ifftshift(to_host(g).reshape((K,) * 3))  # numpy layout
 
 
@@ -111,6 +111,16 @@ def test_outliers_seven_decades(geo):
     assert quiet.sum() > 1000 and e_quiet < 2e-6
     g64 = _spread(geo["p64"], y, torch.complex128)
     assert rel_l2(g64, ref) < 1e-12
+    # the FP64 form in deterministic mode (fixed point, 62-bit scale): same
+    # cell bar with 2^-50 in place of 2^-19, and its FP64 rounding
+    d64 = _spread(geo["p64"], y, torch.complex128, deterministic=True)
+    mag = np.maximum(np.abs(y.real), np.abs(y.imag))
+    A, C = _cover_sums(mag, geo["om"], geo["prm"])
+    bar = (2.0 ** -50 * geo["bmax"] + 1e-12) * C + 8 * 2.0 ** -53 * (A + np.abs(ref))
+    covered = C > 0
+    r64 = np.max(np.abs(d64 - ref)[covered] / bar[covered])
+    say(f"[range] outliers FP64 deterministic: worst err/bar {r64:.3e}, rel-L2 {rel_l2(d64, ref):.2e}")
+    assert r64 <= 1.0 and rel_l2(d64, ref) < 1e-12
 
 
 @pytest.mark.parametrize("scale", [1e-33, 1e-20, 1e35])
@@ -147,8 +157,10 @@ def test_non_finite_values(geo):
     say(f"[range] non-finite cells: oracle {nf_ref.sum()}, FP32 {(~np.isfinite(got)).sum()}, "
         f"FP64 {(~np.isfinite(g64)).sum()}")
     assert nf_ref.sum() >= 5 * J ** 3 // 2
+    d64 = _spread(geo["p64"], y, torch.complex128, deterministic=True)
     assert np.array_equal(~np.isfinite(got), nf_ref)
     assert np.array_equal(~np.isfinite(g64), nf_ref)
+    assert np.array_equal(~np.isfinite(d64), nf_ref)
     # the finite cells against the oracle of the finite values alone
     yf = y.copy()
     yf[bad] = 0.0
