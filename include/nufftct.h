@@ -154,6 +154,22 @@ int nufftct_autotune_radial(int64_t N, int64_t K, int J, int kernel, double beta
 int nufftct_forward(nufftct_plan* plan, const void* vol, void* out, int flags, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the forward
+ * operator of nufftct_forward, same arguments and results, with its workspace
+ * (the K^3 spectrum grid and, with NUFFTCT_RADIAL, the M values ahead of the
+ * radial stage) in one static device array of 64 MiB that the library holds
+ * on every GPU it runs on until the process ends, instead of the plan's.  The
+ * call allocates nothing.  Plans whose workspace exceeds 64 MiB (K^3 x 8 bytes
+ * for FP32 plus M x 8 with NUFFTCT_RADIAL; twice that for FP64) are rejected
+ * with NUFFTCT_EINVAL.  Every call on a GPU shares that GPU's array, which
+ * keeps the last call's contents: calls that overlap on one GPU (different
+ * streams, or host threads) race and must be serialised by the caller.
+ */
+int nufftct_forward_noalloc(nufftct_plan* plan, const void* vol, void* out, int flags,
+                            void* stream);
+
+/*
  * Adjoint (exact conjugate transpose of nufftct_forward with the same flags):
  * in (device, M complex) -> vol (device, N^3 complex, overwritten).  With
  * NUFFTCT_DETERMINISTIC in flags the result is bitwise reproducible in both

@@ -147,6 +147,18 @@ class Plan:
                                                C.c_void_p(_stream_handle(stream))))
         return out
 
+    def forward_noalloc(self, x, out, *, radial: bool = True, deriv: bool = True, stream=None):
+        """forward() with its workspace in the library's static 64 MiB device
+        array: no device allocation in the call (the output must be given).
+        Calls on one GPU must not overlap."""
+        radial = radial and self.n_r > 0
+        _check_tensor(x, self.N ** 3, self.dtype, "x")
+        _check_tensor(out, self.M, self.dtype, "out")
+        _lib.check(_lib.load().nufftct_forward_noalloc(self._ptr, x.data_ptr(), out.data_ptr(),
+                                                       self._flags(radial, deriv),
+                                                       C.c_void_p(_stream_handle(stream))))
+        return out
+
     def adjoint(self, y, out=None, *, radial: bool = True, deriv: bool = True,
                 deterministic: bool = False, stream=None):
         """(L, n_r) or (M,) -> vol (N,N,N): exact conjugate transpose of forward.

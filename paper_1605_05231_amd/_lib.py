@@ -31,6 +31,7 @@ SIGNATURES = {
                                           C.POINTER(C.c_int), C.POINTER(C.c_double), _p]),
     "nufftct_forward": (C.c_int, [_p, _p, _p, C.c_int, _p]),
     "nufftct_adjoint": (C.c_int, [_p, _p, _p, C.c_int, _p]),
+    "nufftct_forward_noalloc": (C.c_int, [_p, _p, _p, C.c_int, _p]),
     "nufftct_radial_quadrature": (C.c_int, [_dp, _i64, _dp, _i64, _dp]),
     "nufftct_set_line_weights": (C.c_int, [_p, _dp, _p]),
     "nufftct_reconstruct": (C.c_int, [_p, _p, _p, _p]),

@@ -791,6 +791,48 @@ static int forward_impl(nufftct_plan* p, const void* vol, void* out, int flags, 
   return NUFFTCT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Forward operator with its workspace (the K^3 spectrum grid, then the M
+// interpolated values ahead of the radial stage) in one static device array
+// instead of the plan's: nothing is allocated per call, so that callers who
+// cannot call hipMalloc (code under graph capture, tight serving loops) can
+// use it.  The array is a host-side stand-in in host code; its device address
+// is taken once per device with hipGetSymbolAddress and used everywhere.
+#define NUFFTCT_STATIC_SCRATCH_BYTES (64ull << 20)
+static __device__ __align__(256) unsigned char scratch[NUFFTCT_STATIC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64] = {nullptr};
+
+static int scratch_address(void** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(NUFFTCT_EUNSUPPORTED, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return NUFFTCT_OK;
+}
+
+template <typename T>
+static int forward_noalloc_impl(nufftct_plan* p, const void* vol, void* out, int flags,
+                                hipStream_t st, unsigned char* ws) {
+  void* grid = ws;
+  void* tmp = ws + p->grid_bytes;  // grid_bytes is a multiple of 256
+  STAGE_TRY(launch_pad_fft<T>(*p, vol, grid, st, true));
+  if (flags & NUFFTCT_RADIAL) {
+    STAGE_TRY(launch_interp<T>(*p, grid, tmp, st));
+    STAGE_TRY(launch_radial<T>(*p, tmp, out, false, (flags & NUFFTCT_DERIV) != 0, st));
+  } else {
+    STAGE_TRY(launch_interp<T>(*p, grid, out, st));
+  }
+  return NUFFTCT_OK;
+}
+
 template <typename T>
 static int adjoint_impl(nufftct_plan* p, const void* in, void* vol, int flags, hipStream_t st) {
   const void* src = in;
@@ -946,6 +988,24 @@ int nufftct_forward(nufftct_plan* p, const void* vol, void* out, int flags, void
   hipStream_t st = (hipStream_t)stream;
   return p->precision == NUFFTCT_FP32 ? forward_impl<float>(p, vol, out, flags, st)
                                       : forward_impl<double>(p, vol, out, flags, st);
+}
+
+int nufftct_forward_noalloc(nufftct_plan* p, const void* vol, void* out, int flags, void* stream) {
+  int rc = check_call(p, vol, out, flags);
+  if (rc) return rc;
+  const size_t need = p->grid_bytes + ((flags & NUFFTCT_RADIAL) ? p->tmp_bytes : 0);
+  if (need > NUFFTCT_STATIC_SCRATCH_BYTES)
+    return fail(NUFFTCT_EINVAL,
+                "nufftct_forward_noalloc: the plan needs %zu bytes of workspace (K^3 grid%s), "
+                "more than the %llu-byte static scratch array",
+                need, (flags & NUFFTCT_RADIAL) ? " and M values" : "",
+                (unsigned long long)NUFFTCT_STATIC_SCRATCH_BYTES);
+  void* ws = nullptr;
+  if ((rc = scratch_address(&ws))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  return p->precision == NUFFTCT_FP32
+             ? forward_noalloc_impl<float>(p, vol, out, flags, st, (unsigned char*)ws)
+             : forward_noalloc_impl<double>(p, vol, out, flags, st, (unsigned char*)ws);
 }
 
 int nufftct_adjoint(nufftct_plan* p, const void* in, void* vol, int flags, void* stream) {
