@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libnufftct.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["plan.cpp", "tables.cpp", "batch.cpp", "umbrella.cpp", "k_fft_f32.hip", "k_fft_f64.hip",
+SOURCES = ["plan.cpp", "host_plan.cpp", "tables.cpp", "batch.cpp", "umbrella.cpp", "k_fft_f32.hip", "k_fft_f64.hip",
            "k_grid_f32.hip", "k_grid_f64.hip", "k_umbrella.hip"]
 
 ARCH = "gfx950"
@@ -21,7 +21,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           # packed FP32 instructions are disabled for every HIP translation unit
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include"), "-Wno-unused-command-line-argument"]
-HOST_ONLY = {"plan.cpp": ["-ffp-contract=off"], "tables.cpp": ["-ffp-contract=off"],
+HOST_ONLY = {"plan.cpp": ["-ffp-contract=off"], "host_plan.cpp": ["-ffp-contract=off"],
+             "tables.cpp": ["-ffp-contract=off"],
              "batch.cpp": [], "umbrella.cpp": []}
 
 

@@ -14,6 +14,7 @@
 #include <thread>
 #include <vector>
 
+#include "host_plan.h"
 #include "plan.h"
 #include "tables.h"
 
@@ -64,223 +65,6 @@ static int env_int(const char* name, int dflt) {
   const char* v = getenv(name);
   if (!v || !*v) return dflt;
   return atoi(v);
-}
-
-// ---------------------------------------------------------------------------
-// Binning: first tap per axis, bit-identical to the device rule.
-#pragma clang fp contract(off)
-static inline void host_first_taps(const double* om, int J, int64_t K, double gamma,
-                                   int (&first)[3]) {
-  for (int d = 0; d < 3; ++d) {
-    const double t = om[d] / gamma;
-    const double tj = t - 0.5 * (double)J;
-    const double k0 = std::floor(tj);
-    int64_t f = (int64_t)k0 + 1 + K / 2;
-    f %= K;
-    if (f < 0) f += K;
-    first[d] = (int)f;
-  }
-}
-
-static void point_omega(const nufftct_plan& p, const std::vector<double>& geom, int64_t i,
-                        double (&om)[3]) {
-  if (p.radial) {
-    const int64_t l = i / p.n_r;
-    const int64_t c = i - l * p.n_r;
-    const double dr = (2.0 * M_PI) / (double)p.n_r;
-    const double r = (double)(c - p.n_r / 2) * dr;
-    om[0] = r * geom[3 * l + 0];
-    om[1] = r * geom[3 * l + 1];
-    om[2] = r * geom[3 * l + 2];
-  } else {
-    om[0] = geom[3 * i + 0];
-    om[1] = geom[3 * i + 1];
-    om[2] = geom[3 * i + 2];
-  }
-}
-#pragma clang fp contract(on)
-
-struct Binning {
-  std::vector<int32_t> perm;    // interpolation order
-  std::vector<int32_t> perm_s;  // spreading order (same tasks)
-  std::vector<TileTask> tasks;
-  std::vector<int32_t> bin_tasks;  // nbins + 1 offsets into tasks
-};
-
-// Sort points by the tile of their first tap and cut every bin into tasks of
-// at most max_pts points.  Within a task the points are then ordered by the
-// LDS bank of their first tap's cell in the staged halo tile, once for each
-// of the two kernels that read the order:
-//   spreading: points that share their first tap cell are paired (one lane
-//     spreads both, summing their contributions to each of the J^3 cells
-//     before one LDS atomic); the pairs come first, then the unpaired
-//     points (FP32 with Kaiser-Bessel weights; the other kernels spread one
-//     point at a time, and their tasks hold no pairs).  Cell c = (l0 S + l1) S + l2 (S = tile + J - 1); pairs, then
-//     singles, dealt round-robin over the residues c mod 32, so the lanes of
-//     a wave start on distinct banks and a tap offset shared by all lanes
-//     keeps them so;
-//   interpolation (FP32): rows padded to even pitch S2, cell
-//     c = (l0 S + l1) S2 + l2; even cells first, then odd ones (a wave's
-//     row reads then share one alignment), each class dealt round-robin over
-//     its 16 residues mod 32.  FP64 interpolation uses the spreading order.
-static void build_bins(const nufftct_plan& p, const std::vector<double>& geom, Binning& B) {
-  const int64_t M = p.M;
-  const int nb = p.nb, T = p.tile, J = p.J;
-  const int S = T + J - 1;
-  const bool pairs = p.precision == NUFFTCT_FP32;
-  // the FP32 spreading with Kaiser-Bessel weights sums paired points'
-  // contributions; the other kernels spread one point at a time
-  const bool pair_spread = pairs && p.kernel != NUFFTCT_KERNEL_MINMAX_KB;
-  const int S2 = pairs ? S + (S & 1) : S;
-  const int64_t nbins = (int64_t)nb * nb * nb;
-  std::vector<int32_t> key(M);
-  std::vector<uint8_t> res_s(M), res_i(M);
-  std::vector<uint16_t> lcell(M);  // first tap cell within its tile
-  const double gamma = (2.0 * M_PI) / (double)p.K;
-  unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  if (M < 200000) nth = 1;
-  auto parallel = [&](int64_t n, auto&& fn) {
-    std::vector<std::thread> th;
-    for (unsigned t = 0; t < nth; ++t)
-      th.emplace_back([&, t]() { fn(n * t / nth, n * (t + 1) / nth); });
-    for (auto& t : th) t.join();
-  };
-  parallel(M, [&](int64_t a, int64_t b) {
-    for (int64_t i = a; i < b; ++i) {
-      double om[3];
-      int first[3];
-      point_omega(p, geom, i, om);
-      host_first_taps(om, J, p.K, gamma, first);
-      key[i] = (int32_t)(((int64_t)(first[0] / T) * nb + first[1] / T) * nb + first[2] / T);
-      const int r01 = (first[0] % T) * S + first[1] % T;
-      res_s[i] = (uint8_t)((r01 * S + first[2] % T) & 31);
-      lcell[i] = (uint16_t)(((first[0] % T) * T + first[1] % T) * T + first[2] % T);
-      res_i[i] = (uint8_t)((r01 * S2 + first[2] % T) & 31);
-    }
-  });
-  std::vector<int64_t> off(nbins + 1, 0);
-  for (int64_t i = 0; i < M; ++i) off[key[i] + 1]++;
-  for (int64_t k = 0; k < nbins; ++k) off[k + 1] += off[k];
-  B.perm_s.resize(M);
-  {
-    std::vector<int64_t> pos(off.begin(), off.end() - 1);
-    for (int64_t i = 0; i < M; ++i) B.perm_s[pos[key[i]]++] = (int32_t)i;
-  }
-  B.tasks.clear();
-  B.bin_tasks.assign(nbins + 1, 0);
-  for (int64_t b = 0; b < nbins; ++b) {
-    B.bin_tasks[b] = (int32_t)B.tasks.size();
-    const int64_t s = off[b], e = off[b + 1];
-    for (int64_t q = s; q < e; q += p.max_pts) {
-      TileTask t;
-      t.bin = (int32_t)b;
-      t.start = (int32_t)q;
-      t.count = (int32_t)std::min<int64_t>(p.max_pts, e - q);
-      t.npairs = 0;
-      B.tasks.push_back(t);
-    }
-  }
-  B.bin_tasks[nbins] = (int32_t)B.tasks.size();
-  B.perm = B.perm_s;
-  // Reorder pts[0..n) by residue: classes of residues r = cls, cls + step, ...
-  // in turn, each dealt round-robin over its residues.
-  struct Deal {
-    std::vector<int32_t> tmp, bucket, cnt = std::vector<int32_t>(33), fill;
-    void run(int32_t* pts, int n, const uint8_t* res, int step) {
-      std::fill(cnt.begin(), cnt.end(), 0);
-      for (int i = 0; i < n; ++i) cnt[res[pts[i]] + 1]++;
-      for (int r = 0; r < 32; ++r) cnt[r + 1] += cnt[r];
-      tmp.assign(pts, pts + n);
-      bucket.resize(n);
-      fill.assign(cnt.begin(), cnt.end() - 1);
-      for (int i = 0; i < n; ++i) bucket[fill[res[tmp[i]]]++] = tmp[i];
-      int o = 0;
-      for (int cls = 0; cls < step; ++cls) {
-        int left = 0;
-        for (int r = cls; r < 32; r += step) left += cnt[r + 1] - cnt[r];
-        if (step == 2) {
-          // groups of 16 points (one LDS pass of 16-byte reads) take one
-          // point from each of the 16 fullest residues of the class, so the
-          // buckets drain evenly and late groups keep distinct residues
-          int rs[16], nr = 0, take[32], rem[32];
-          for (int r = cls; r < 32; r += step) {
-            rs[nr++] = r;
-            take[r] = cnt[r];
-            rem[r] = cnt[r + 1] - cnt[r];
-          }
-          while (left > 0) {
-            std::stable_sort(rs, rs + nr, [&](int x, int y) { return rem[x] > rem[y]; });
-            int g = 0;
-            for (int k = 0; k < nr && g < 16 && rem[rs[k]] > 0; ++k, ++g) {
-              pts[o++] = bucket[take[rs[k]]++];
-              --rem[rs[k]];
-              --left;
-            }
-            while (g < 16 && left > 0) {  // fewer than 16 residues left
-              int best = rs[0];
-              for (int k = 1; k < nr; ++k)
-                if (rem[rs[k]] > rem[best]) best = rs[k];
-              pts[o++] = bucket[take[best]++];
-              --rem[best];
-              --left;
-              ++g;
-            }
-          }
-          continue;
-        }
-        for (int round = 0; left > 0; ++round)
-          for (int r = cls; r < 32; r += step)
-            if (cnt[r] + round < cnt[r + 1]) {
-              pts[o++] = bucket[cnt[r] + round];
-              --left;
-            }
-      }
-    }
-  };
-  parallel((int64_t)B.tasks.size(), [&](int64_t a, int64_t b) {
-    Deal d;
-    std::vector<int32_t> sorted, first_of, singles, idx;
-    std::vector<uint8_t> res_pair;
-    for (int64_t k = a; k < b; ++k) {
-      TileTask& t = B.tasks[k];
-      int32_t* ps = B.perm_s.data() + t.start;
-      if (!pair_spread) {  // no paired spreading: points dealt one by one
-        d.run(ps, t.count, res_s.data(), 1);
-        t.npairs = 0;
-        d.run(B.perm.data() + t.start, t.count, pairs ? res_i.data() : res_s.data(), pairs ? 2 : 1);
-        continue;
-      }
-      // pair the points of each first tap cell (in point order within it)
-      sorted.assign(ps, ps + t.count);
-      std::stable_sort(sorted.begin(), sorted.end(),
-                       [&](int32_t x, int32_t y) { return lcell[x] < lcell[y]; });
-      first_of.clear();
-      singles.clear();
-      res_pair.clear();
-      for (int i = 0; i < t.count;) {
-        int j = i;
-        while (j < t.count && lcell[sorted[j]] == lcell[sorted[i]]) ++j;
-        for (int q = i; q + 1 < j; q += 2) {
-          first_of.push_back(q);  // pair (sorted[q], sorted[q + 1])
-          res_pair.push_back(res_s[sorted[q]]);
-        }
-        if ((j - i) & 1) singles.push_back(sorted[j - 1]);
-        i = j;
-      }
-      const int np = (int)first_of.size();
-      idx.resize(np);
-      for (int q = 0; q < np; ++q) idx[q] = q;
-      d.run(idx.data(), np, res_pair.data(), 1);
-      for (int q = 0; q < np; ++q) {
-        ps[2 * q] = sorted[first_of[idx[q]]];
-        ps[2 * q + 1] = sorted[first_of[idx[q]] + 1];
-      }
-      d.run(singles.data(), (int)singles.size(), res_s.data(), 1);
-      std::copy(singles.begin(), singles.end(), ps + 2 * np);
-      t.npairs = np;
-      d.run(B.perm.data() + t.start, t.count, pairs ? res_i.data() : res_s.data(), pairs ? 2 : 1);
-    }
-  });
 }
 
 // ---------------------------------------------------------------------------
@@ -562,8 +346,21 @@ static int create(nufftct_plan** out, int64_t N, int64_t K, int J, int kernel, d
 
   // binning
   {
-    Binning B;
-    build_bins(*p, g, B);
+    hostplan::Binning B;
+    hostplan::BinParams bp;
+    bp.M = p->M;
+    bp.K = p->K;
+    bp.n_r = p->n_r;
+    bp.J = J;
+    bp.tile = p->tile;
+    bp.nb = p->nb;
+    bp.max_pts = p->max_pts;
+    bp.radial = p->radial;
+    bp.fp32 = precision == NUFFTCT_FP32;
+    // the FP32 spreading with Kaiser-Bessel weights sums paired points'
+    // contributions; the other kernels spread one point at a time
+    bp.pair_spread = bp.fp32 && kernel != NUFFTCT_KERNEL_MINMAX_KB;
+    hostplan::build_bins(bp, g, B);
     p->ntasks = (int64_t)B.tasks.size();
     {
       // cut the task list into NUFFTCT_NUM_XCD contiguous ranges of equal point count

@@ -9,6 +9,7 @@
 
 #include "../../include/nufftct.h"
 #include "cx.h"
+#include "host_plan.h"
 
 // Degree of the per-tap weight polynomials (piecewise Horner form of the
 // interpolation kernel on each unit interval), per precision.
@@ -36,13 +37,6 @@ struct PointGeom {
   int K;
 };
 
-struct TileTask {
-  int32_t bin;     // linear tile index (b0 * nb + b1) * nb + b2
-  int32_t start;   // first entry in the permutation
-  int32_t count;   // number of points
-  int32_t npairs;  // spreading order: its first 2 npairs entries are npairs
-                   // pairs of points that share their first tap cell
-};
 
 struct nufftct_plan {
   int64_t N = 0, K = 0, M = 0, n_r = 0, n_lines = 0;
