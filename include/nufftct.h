@@ -289,6 +289,54 @@ int nufftct_umbrella_resample(nufftct_umbrella* u, const void* radial, void* out
 int nufftct_umbrella_destroy(nufftct_umbrella* u);
 
 /*
+ * Radial -> umbrella resampling, method 1 of Section 2.1.3 (eq 2.11:
+ * x~ = T_sparse F P F^-1 x): the ideal interpolator of eq 2.8 (a periodic
+ * sinc per axis, eq 2.2-2.7) computed as an oversampled NUFFT in the
+ * (phi, theta, rho) index space of the radial grid.  Same scan geometry,
+ * radial grid, target index coordinates and layouts as method 2 above;
+ * nufftct_umbrella_resample and nufftct_umbrella_destroy serve both methods.
+ *
+ * Steps: F^-1, the inverse DFT of the N_phi x N_theta x N_r samples with the
+ * 1/N_d that reproduces the samples, over the centred band m_d in
+ * [-N_d/2, N_d/2); P, the Kaiser-Bessel scaling s_d(m_d) = 1/Psi(m_d/K_d)
+ * (beta = 2.34 J) and zero padding to K_d = 2 N_d (the factor-2 oversampling
+ * the section prefers for this kernel); F, the forward FFT of the K grid;
+ * T_sparse, the J^3 Kaiser-Bessel taps at grid coordinate 2 t_d (t_d the
+ * target's index coordinate), taps k0+1..k0+J with k0 = floor(2 t_d - J/2),
+ * every axis wrapped mod K_d.  Every axis is treated as periodic, as the DFT
+ * makes it: exact for phi, for rho where the Radon values vanish beyond the
+ * object; targets in theta's unsampled polar caps get the periodic
+ * interpolant's values (method 2 gives them zero taps).
+ *
+ * n_phi, n_theta, n_r: each even, in 8..512, with 2n = 2^a 3^b 5^c and among
+ * the compiled lengths (8 12 16 20 24 30 32 36 40 48 60 64 72 80 90 96 120
+ * 128 144 160 180 192 240 256 288 320 360 384 480 512); J in [2, 8].  Create
+ * allocates the K_0 K_1 K_2 complex grid workspace on the current device
+ * (8 x the radial data) and small tables; resample calls on one object
+ * share that workspace, so calls that overlap race.  Errors: as method 2,
+ * plus EUNSUPPORTED (length not compiled, weight fit) and ENOMEM.
+ */
+int nufftct_umbrella1_create(nufftct_umbrella** out, int64_t n_proj, int64_t n_alpha,
+                             int64_t n_t, double source_radius, double source_detector,
+                             double detector_side, int64_t n_phi, int64_t n_theta,
+                             double theta0, double dtheta, int64_t n_r, int J, int precision,
+                             void* stream);
+/* Method 1 only: K3 (host, 3 values) receives the grid sizes (K_phi, K_theta, K_r). */
+int nufftct_umbrella_grid_shape(const nufftct_umbrella* u, int64_t* K3);
+/*
+ * Method 1 only, one step at a time (device buffers, not aliasing):
+ *   NUFFTCT_UMB_STAGE_GRID:   in = radial samples [phi][theta][rho] ->
+ *                             out = F P F^-1 D on the K grid [K_phi][K_theta][K_r],
+ *                             frequency kappa at index kappa mod K_d (out is
+ *                             overwritten in full);
+ *   NUFFTCT_UMB_STAGE_GATHER: in = such a grid -> out = umbrella samples [k][i][j].
+ */
+#define NUFFTCT_UMB_STAGE_GRID 0
+#define NUFFTCT_UMB_STAGE_GATHER 1
+int nufftct_umbrella_stage(nufftct_umbrella* u, int stage, const void* in, void* out,
+                           void* stream);
+
+/*
  * Batch of independent volumes of uneven size (each with its own radial
  * direction set).  The batch owns one plan per volume (created with the
  * given parameters; J, kernel, beta and precision are shared), each with its

@@ -56,30 +56,36 @@ SO_MM, SD_MM, DET_MM, OBJ_MM = 1100.0, 1500.0, 512.0, 360.0
 
 def geometry(N: int, n_proj: int, n_alpha: int, n_t: int):
     """Plane normals (P, 3) and signed distances (P,) of the umbrella samples."""
+    return geometry_at(N, n_proj, n_alpha, n_t, np.arange(n_proj * n_alpha * n_t))
+
+
+def geometry_at(N: int, n_proj: int, n_alpha: int, n_t: int, samples):
+    """As geometry, for the samples p = (k * n_alpha + i) * n_t + j listed."""
     R_s = N * SO_MM / OBJ_MM
     D_sd = N * SD_MM / OBJ_MM
     side = N * DET_MM / OBJ_MM
-    lam = 2 * math.pi * np.arange(n_proj) / n_proj
-    alpha = math.pi * np.arange(n_alpha) / n_alpha
-    t = (np.arange(n_t) - n_t // 2) * (side / n_t)
-    nh = np.empty((n_proj, n_alpha, n_t, 3))
-    rho = np.empty((n_proj, n_alpha, n_t))
-    for k, lm in enumerate(lam):
+    samples = np.asarray(samples, dtype=np.int64).reshape(-1)
+    nh = np.empty((len(samples), 3))
+    rho = np.empty(len(samples))
+    for q, p in enumerate(samples):
+        k, rem = divmod(int(p), n_alpha * n_t)
+        i, j = divmod(rem, n_t)
+        lm = 2 * math.pi * k / n_proj
+        al = math.pi * i / n_alpha
+        tj = (j - n_t // 2) * (side / n_t)
         shat = np.array([math.cos(lm), math.sin(lm), 0.0])
         s = R_s * shat
         c = s - D_sd * shat
         u = np.array([-math.sin(lm), math.cos(lm), 0.0])
         v = np.array([0.0, 0.0, 1.0])
-        for i, al in enumerate(alpha):
-            e = -math.sin(al) * u + math.cos(al) * v
-            w = math.cos(al) * u + math.sin(al) * v
-            for j, tj in enumerate(t):
-                q = c - s + tj * w
-                n = np.cross(e, q)
-                n = n / np.linalg.norm(n)
-                nh[k, i, j] = n
-                rho[k, i, j] = n @ s
-    return nh.reshape(-1, 3), rho.reshape(-1)
+        e = -math.sin(al) * u + math.cos(al) * v
+        w = math.cos(al) * u + math.sin(al) * v
+        qv = c - s + tj * w
+        n = np.cross(e, qv)
+        n = n / np.linalg.norm(n)
+        nh[q] = n
+        rho[q] = n @ s
+    return nh, rho
 
 
 def angles(nh: np.ndarray):

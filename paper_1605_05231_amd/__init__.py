@@ -15,7 +15,7 @@ import numpy as np
 from . import _lib
 from ._lib import (DERIV, DERIV_RADIAL, DETERMINISTIC, FP32, FP64, KERNEL_KB, KERNEL_MINMAX_KB, RADIAL,  # noqa: F401
                    STAGE_IFFT_CROP, STAGE_INTERP, STAGE_NAMES, STAGE_PAD_FFT, STAGE_RADIAL,
-                   STAGE_RADIAL_ADJ, STAGE_SPREAD, NufftError)
+                   STAGE_RADIAL_ADJ, STAGE_SPREAD, UMB_STAGE_GATHER, UMB_STAGE_GRID, NufftError)
 
 __all__ = ["Plan", "Batch", "Umbrella", "NufftProjector", "project", "autotune", "radial_quadrature",
            "NufftError", "version"]
@@ -258,25 +258,36 @@ SCAN_MM = (1100.0, 1500.0, 512.0, 360.0)
 
 
 class Umbrella:
-    """Radial -> umbrella resampling (method 2, eq 2.15) for a circular
-    cone-beam scan; distances in voxels (default: the Section 3.2.1 set-up
-    scaled to an N^3 volume spanning the object)."""
+    """Radial -> umbrella resampling for a circular cone-beam scan: method 2
+    (eq 2.15, the default) or method 1 (eq 2.11, an oversampled NUFFT in the
+    radial grid's index space); distances in voxels (default: the Section
+    3.2.1 set-up scaled to an N^3 volume spanning the object)."""
 
     def __init__(self, N, n_proj, n_alpha, n_t, n_phi, n_theta, n_r, theta0, dtheta, *, J=6,
-                 scan=None, dtype=None):
+                 scan=None, dtype=None, method=2):
         torch = _torch()
         self.dtype = dtype or torch.complex64
         prec = {torch.complex64: FP32, torch.complex128: FP64}[self.dtype]
         if scan is None:
             so, sd, det, obj = SCAN_MM
             scan = (N * so / obj, N * sd / obj, N * det / obj)
+        if method not in (1, 2):
+            raise ValueError("method must be 1 or 2")
+        self.method = method
         self.n_in = int(n_phi) * int(n_theta) * int(n_r)
         self.shape = (int(n_proj), int(n_alpha), int(n_t))
         self._ptr = C.c_void_p()
-        _lib.check(_lib.load().nufftct_umbrella_create(
+        lib = _lib.load()
+        create = lib.nufftct_umbrella1_create if method == 1 else lib.nufftct_umbrella_create
+        _lib.check(create(
             C.byref(self._ptr), int(n_proj), int(n_alpha), int(n_t), float(scan[0]), float(scan[1]),
             float(scan[2]), int(n_phi), int(n_theta), float(theta0), float(dtheta), int(n_r), int(J),
             prec, C.c_void_p(_stream_handle())))
+        self.grid_shape = None
+        if method == 1:
+            K3 = (C.c_int64 * 3)()
+            _lib.check(lib.nufftct_umbrella_grid_shape(self._ptr, K3))
+            self.grid_shape = tuple(int(k) for k in K3)
 
     def resample(self, d, out=None, *, stream=None):
         torch = _torch()
@@ -286,6 +297,27 @@ class Umbrella:
         _check_tensor(out, self.shape[0] * self.shape[1] * self.shape[2], self.dtype, "out")
         _lib.check(_lib.load().nufftct_umbrella_resample(self._ptr, d.data_ptr(), out.data_ptr(),
                                                          C.c_void_p(_stream_handle(stream))))
+        return out
+
+    def stage(self, which, x, out=None, *, stream=None):
+        """Method 1, one step: "grid" (radial samples -> oversampled grid
+        F P F^-1 D, shape grid_shape) or "gather" (grid -> umbrella samples)."""
+        torch = _torch()
+        if self.method != 1:
+            raise ValueError("only method 1 has stages")
+        ncell = self.grid_shape[0] * self.grid_shape[1] * self.grid_shape[2]
+        if which == "grid":
+            code, n_in, shape = UMB_STAGE_GRID, self.n_in, self.grid_shape
+        elif which == "gather":
+            code, n_in, shape = UMB_STAGE_GATHER, ncell, self.shape
+        else:
+            raise ValueError(which)
+        _check_tensor(x, n_in, self.dtype, "x")
+        if out is None:
+            out = torch.empty(shape, dtype=self.dtype, device=x.device)
+        _check_tensor(out, shape[0] * shape[1] * shape[2], self.dtype, "out")
+        _lib.check(_lib.load().nufftct_umbrella_stage(self._ptr, code, x.data_ptr(), out.data_ptr(),
+                                                      C.c_void_p(_stream_handle(stream))))
         return out
 
     def close(self):

@@ -14,7 +14,8 @@ OUT = os.path.join(HERE, "libnufftct.so")
 BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["plan.cpp", "host_plan.cpp", "tables.cpp", "batch.cpp", "umbrella.cpp", "k_fft_f32.hip", "k_fft_f64.hip",
-           "k_grid_f32.hip", "k_grid_f64.hip", "k_umbrella.hip"]
+           "k_grid_f32.hip", "k_grid_f64.hip", "k_umbrella.hip", "k_resample1_f32.hip",
+           "k_resample1_f64.hip"]
 
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

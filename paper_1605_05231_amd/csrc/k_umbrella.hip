@@ -54,33 +54,13 @@ __global__ __launch_bounds__(NT) void k_umbrella(const cx<T>* __restrict__ D,
   const int64_t total = (int64_t)g.n_proj * g.n_alpha * g.n_t;
   const int64_t p = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (p >= total) return;
-  const int j = (int)(p % g.n_t);
-  const int i = (int)((p / g.n_t) % g.n_alpha);
-  const int k = (int)(p / ((int64_t)g.n_t * g.n_alpha));
-  const double pi = 3.14159265358979323846;
-  const double lam = 2.0 * pi * (double)k / (double)g.n_proj;
-  const double al = pi * (double)i / (double)g.n_alpha;
-  const double t = (double)(j - g.n_t / 2) * g.dt;
-  const double cl = cos(lam), sl = sin(lam), ca = cos(al), sa = sin(al);
-  // u = (-sl, cl, 0), v = (0, 0, 1); e = -sa u + ca v; w = ca u + sa v
-  const double e0 = sa * sl, e1 = -sa * cl, e2 = ca;
-  const double w0 = -ca * sl, w1 = ca * cl, w2 = sa;
-  // q = c - s + t w = -D_sd shat + t w
-  const double q0 = -g.D_sd * cl + t * w0, q1 = -g.D_sd * sl + t * w1, q2 = t * w2;
-  double n0 = e1 * q2 - e2 * q1, n1 = e2 * q0 - e0 * q2, n2 = e0 * q1 - e1 * q0;
-  const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
-  n0 /= nn;
-  n1 /= nn;
-  n2 /= nn;
-  const double rho = g.R_s * (n0 * cl + n1 * sl);
-  const double theta = acos(fmin(1.0, fmax(-1.0, n2)));
-  double phi = atan2(n1, n0);
-  if (phi < 0.0) phi += 2.0 * pi;
+  double tp, tt, tr;
+  umbrella_coords(g, p, tp, tt, tr);
   int kp, kt, kr;
   T wp[J], wt[J], wr[J];
-  taps<T, J>(phi * g.inv_dphi, g.beta, g.inv_i0beta, kp, wp);
-  taps<T, J>((theta - g.theta0) * g.inv_dtheta, g.beta, g.inv_i0beta, kt, wt);
-  taps<T, J>(rho + 0.5 * (double)g.n_r, g.beta, g.inv_i0beta, kr, wr);
+  taps<T, J>(tp, g.beta, g.inv_i0beta, kp, wp);
+  taps<T, J>(tt, g.beta, g.inv_i0beta, kt, wt);
+  taps<T, J>(tr, g.beta, g.inv_i0beta, kr, wr);
   cx<T> acc = {0, 0};
 #pragma unroll
   for (int a = 0; a < J; ++a) {
