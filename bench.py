@@ -403,7 +403,8 @@ def bench_umbrella(args):
     """Radial -> umbrella resampling (method 2, eq 2.15) at the 128^3 set-up of
     the cone-beam experiment: the c2 projector output (180 x 90 lines x 256)
     resampled onto 256 projections x 256 x 256 detector lines; Msamples/s =
-    umbrella samples / time of one resampling, for J = 3 (the paper's) and 6."""
+    umbrella samples / time of one resampling, for J = 3 (the paper's) and 6;
+    then method 1 (eq 2.11) at J = 6 with its grid step and gather timed apart."""
     import numpy as np
     import torch
 
@@ -434,6 +435,39 @@ def bench_umbrella(args):
         res[Ju] = ms
         log(f"[bench] umbrella J={Ju}: {ms:.3f} ms -> {P / (ms * 1e-3) / 1e6:.1f} Msamples/s")
         u.close()
+    # method 1 (eq 2.11): the grid step (three in-place axis passes) and the
+    # J^3 gather, timed apart with events on the stream they run on
+    u1 = pkg.Umbrella(N, n_proj, n_alpha, n_t, W.n_phi, W.n_theta, n_r, th[0], th[1] - th[0], J=6,
+                      method=1)
+    out = torch.empty((n_proj, n_alpha, n_t), dtype=torch.complex64, device="cuda")
+    grid = torch.empty(u1.grid_shape, dtype=torch.complex64, device="cuda")
+    for _ in range(args.warmup):
+        u1.resample(d, out=out)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t_grid = t_gather = 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        u1.resample(d, out=out)
+    torch.cuda.synchronize()
+    ms1 = (time.perf_counter() - t0) * 1e3 / args.steps
+    for _ in range(args.steps):
+        ev[0].record()
+        u1.stage("grid", d, out=grid)
+        ev[1].record()
+        u1.stage("gather", grid, out=out)
+        ev[2].record()
+        torch.cuda.synchronize()
+        t_grid += ev[0].elapsed_time(ev[1])
+        t_gather += ev[1].elapsed_time(ev[2])
+    t_grid /= args.steps
+    t_gather /= args.steps
+    n_in = W.n_phi * W.n_theta * n_r
+    grid_bytes = 21 * 8 * n_in  # input once, then 2+4+8 times it written and 2+4 read
+    log(f"[bench] umbrella method 1 J=6: {ms1:.3f} ms -> {P / (ms1 * 1e-3) / 1e6:.1f} Msamples/s; "
+        f"grid step {t_grid:.3f} ms ({grid_bytes / (t_grid * 1e-3) / 1e9:.0f} GB/s algorithmic), "
+        f"gather {t_gather:.3f} ms")
+    u1.close()
     print(json.dumps({
         "metric": "radial-to-umbrella resampling (method 2) Msamples/s at 128³",
         "value": round(P / (res[6] * 1e-3) / 1e6, 2), "unit": "Msamples/s", "n_gpus": 1,
@@ -443,6 +477,14 @@ def bench_umbrella(args):
         "config": {"workload": "c2 derivative-Radon values (180 x 90 lines x 256) -> 256 projections "
                                "x 256 x 256 umbrella planes, J = 6", "samples": P},
         "J3_ms": round(res[3], 4),
+        "method1": {
+            "ms": round(ms1, 4), "Msamples_s": round(P / (ms1 * 1e-3) / 1e6, 2), "J": 6,
+            "grid_ms": round(t_grid, 4), "gather_ms": round(t_gather, 4),
+            "grid_cells": int(u1.grid_shape[0] * u1.grid_shape[1] * u1.grid_shape[2]),
+            "roofline_grid": {"bound": "hbm", "alg_bytes": grid_bytes,
+                              "achieved": round(grid_bytes / (t_grid * 1e-3) / 1e9, 1), "peak": 8000.0,
+                              "unit": "GB/s", "frac": round(grid_bytes / (t_grid * 1e-3) / 8e12, 4)},
+        },
     }), flush=True)
 
 

@@ -3,15 +3,17 @@ dynamic range, tiny or huge magnitudes and non-finite values, checked cell by
 cell against the oracle.
 
 The FP32 spreading accumulates integers: a value v of magnitude
-a = max(|re v|, |im v|) is rounded on a fixed-point scale shared by the values
-of its magnitude class within its task, which bounds each of its
-contributions' rounding error by a * B * 2^-19, B the largest sum over a halo
-cell of the products of the weight magnitudes (at most B_max, the same sum over
-all points, computed here from the oracle's weights).  With the polynomial
-weights' fit error (<= 1e-7 per axis) and the FP32 products and additions,
-every cell k then satisfies
+a = max(|re v|, |im v|) is rounded on a fixed-point scale s = 2^30 / (top B)
+shared by the values of its magnitude class within its task (top < 2^c, the
+class's bound, and the class holds the binades within CLASS_BITS = 16 of c,
+so top < 2^(CLASS_BITS + 1) a), B the largest sum over a halo cell of the
+products of the weight magnitudes (at most B_max, the same sum over all
+points, computed here from the oracle's weights).  Each contribution's
+rounding error is then <= 0.5 / s < a B 2^(CLASS_BITS - 30).  With the
+polynomial weights' fit error (<= 1e-7 per axis) and the FP32 products and
+additions, every cell k satisfies
 
-    |spread_k - oracle_k| <= (2^-19 B_max + 4e-7) C_k + 8 eps (A_k + |oracle_k|),
+    |spread_k - oracle_k| <= (2^(CLASS_BITS-30) B_max + 4e-7) C_k + 8 eps (A_k + |oracle_k|),
 
 C_k = sum over the points whose footprint covers k of a_p, A_k the same sum
 weighted by the weight magnitudes, eps = 2^-24.  A single fixed-point scale per
@@ -30,6 +32,7 @@ from tests.gpu_util import rel_l2, require_gpu, say, to_dev, to_host
 pytestmark = pytest.mark.gpu
 
 N, K, J, N_R = 32, 64, 6, 64
+CLASS_BITS = 16  # the binades one fixed-point scale of the spreading serves
 
 
 def _cover_sums(mag, om, prm):
@@ -75,7 +78,7 @@ def _check_cells(geo, y, got, label):
     mag = np.maximum(np.abs(y.real), np.abs(y.imag))
     A, C = _cover_sums(mag, geo["om"], geo["prm"])
     eps = 2.0 ** -24
-    bar = (2.0 ** -19 * geo["bmax"] + 4e-7) * C + 8 * eps * (A + np.abs(ref))
+    bar = (2.0 ** (CLASS_BITS - 30) * geo["bmax"] + 4e-7) * C + 8 * eps * (A + np.abs(ref))
     err = np.abs(got - ref)
     covered = C > 0
     ratio = np.max(err[covered] / bar[covered])
@@ -111,12 +114,12 @@ def test_outliers_seven_decades(geo):
     assert quiet.sum() > 1000 and e_quiet < 2e-6
     g64 = _spread(geo["p64"], y, torch.complex128)
     assert rel_l2(g64, ref) < 1e-12
-    # the FP64 form in deterministic mode (fixed point, 62-bit scale): same
-    # cell bar with 2^-50 in place of 2^-19, and its FP64 rounding
+    # the FP64 form in deterministic mode (fixed point, scale 2^62 / (top B)):
+    # the same cell bar with 2^(CLASS_BITS - 62), and its FP64 rounding
     d64 = _spread(geo["p64"], y, torch.complex128, deterministic=True)
     mag = np.maximum(np.abs(y.real), np.abs(y.imag))
     A, C = _cover_sums(mag, geo["om"], geo["prm"])
-    bar = (2.0 ** -50 * geo["bmax"] + 1e-12) * C + 8 * 2.0 ** -53 * (A + np.abs(ref))
+    bar = (2.0 ** (CLASS_BITS - 62) * geo["bmax"] + 1e-12) * C + 8 * 2.0 ** -53 * (A + np.abs(ref))
     covered = C > 0
     r64 = np.max(np.abs(d64 - ref)[covered] / bar[covered])
     say(f"[range] outliers FP64 deterministic: worst err/bar {r64:.3e}, rel-L2 {rel_l2(d64, ref):.2e}")
