@@ -61,6 +61,7 @@ extern "C" {
 typedef struct nufftct_plan nufftct_plan;
 typedef struct nufftct_batch nufftct_batch;
 typedef struct nufftct_umbrella nufftct_umbrella;
+typedef struct nufftct_grangeat nufftct_grangeat;
 
 /* status codes */
 #define NUFFTCT_OK 0
@@ -335,6 +336,64 @@ int nufftct_umbrella_grid_shape(const nufftct_umbrella* u, int64_t* K3);
 #define NUFFTCT_UMB_STAGE_GATHER 1
 int nufftct_umbrella_stage(nufftct_umbrella* u, int stage, const void* in, void* out,
                            void* stream);
+
+/*
+ * Umbrella derivative-Radon values -> cone-beam projections: the Grangeat
+ * step in reverse (Section 2.2.2, Figures 2.14-2.15; its steps' costs in
+ * eq 2.21-2.24), one projection per umbrella subset.  The section defers its
+ * weights to an earlier report; they are taken from Grangeat's relation in
+ * its textbook form.  Per projection k:
+ *   1. de-postweighting: p'_ij = -U[k][i][j] R^2 / (R^2 + s'_j^2), the
+ *      derivative of the 2D Radon transform of the pre-weighted projection on
+ *      the virtual detector through the axis (s'_j = t_j R / D); the minus
+ *      turns the umbrella orientation (normal (e x q)/|e x q|) into the one
+ *      whose distance grows with s';
+ *   2. radial FFTs of the lines zero-padded to 2n samples, times
+ *      -i sign(k) / (2 pi) dalpha dk (inversion from derivative data needs no
+ *      ramp); the k = 0 bin takes dalpha dk^2 / 6 P(alpha, 0) (the
+ *      Euler-Maclaurin correction of the trapezoidal rule on |k| P at its
+ *      kink, P(alpha, 0) = -int s' p' ds'); the Nyquist bin nothing;
+ *   3. 2D NUFFT transpose: Kaiser-Bessel spreading (J taps per axis, beta =
+ *      2.34 J, the neighbour rule of the projector) of the polar points
+ *      omega = pi (m - n)/n (cos alpha_i, sin alpha_i) onto the 2n x 2n grid,
+ *      the unnormalised inverse 2D FFT, the crop to n x n and 1/Psi per axis;
+ *   4. de-preweighting: X = g sqrt(R^2 + u'^2 + v'^2) / R.
+ * Geometry as the umbrella resampling (source radius R, source-detector
+ * distance D, detector side, alpha_i = pi i / n_alpha, t_j = (j - n/2) side/n,
+ * pixel (a, b) at u = (a - n/2) side/n, v = (b - n/2) side/n).  Projections
+ * are exact (to the O(dk^4) quadrature error) where the object's shadow lies
+ * inside the detector's inscribed disc: the umbrella lines reach |t| <= side/2.
+ *
+ * umbrella (device): n_proj * n_alpha * n complex, [k][i][j] (the umbrella
+ * resampling's output with n_t = n).  out (device): n_proj * n * n complex,
+ * [k][b][a] (v row, u column).  Complex64 for FP32, complex128 for FP64.
+ * n: one of the compiled sizes 16 24 32 48 64 96 128 160 192 256 320 384
+ * 512; J in [2, 8] (the paper's [5 5]: J = 5).  Create allocates on the current
+ * device the spectra (n_alpha * 2n * n_proj complex), the row-pass workspace
+ * (n_proj * 2n * n complex) and the per-cell gather lists of the polar points
+ * (n_alpha * 2n * J^2 entries); calls on one object share them, so calls that
+ * overlap race.  Errors: EINVAL (counts, distances, J, NULL or aliasing
+ * buffers), EUNSUPPORTED (n not compiled), ENOMEM, EHIP.
+ */
+int nufftct_grangeat_create(nufftct_grangeat** out, int64_t n_proj, int64_t n_alpha, int64_t n,
+                            double source_radius, double source_detector, double detector_side,
+                            int J, int precision, void* stream);
+int nufftct_grangeat_project(nufftct_grangeat* g, const void* umbrella, void* out, void* stream);
+/*
+ * One step at a time (device buffers, not aliasing):
+ *   NUFFTCT_GR_STAGE_SPECTRA:     in = umbrella samples [k][i][j] -> out =
+ *                                 filtered spectra c[(i * 2n + m) * n_proj + k]
+ *                                 (steps 1-2; frequency (m - n) dk);
+ *   NUFFTCT_GR_STAGE_BACKPROJECT: in = such spectra -> out = projections
+ *                                 [k][b][a] (steps 3-4).
+ * n_entries receives the number of gather-list entries (host pointer).
+ */
+#define NUFFTCT_GR_STAGE_SPECTRA 0
+#define NUFFTCT_GR_STAGE_BACKPROJECT 1
+int nufftct_grangeat_stage(nufftct_grangeat* g, int stage, const void* in, void* out,
+                           void* stream);
+int nufftct_grangeat_info(const nufftct_grangeat* g, int64_t* n_entries);
+int nufftct_grangeat_destroy(nufftct_grangeat* g);
 
 /*
  * Batch of independent volumes of uneven size (each with its own radial

@@ -15,9 +15,10 @@ import numpy as np
 from . import _lib
 from ._lib import (DERIV, DERIV_RADIAL, DETERMINISTIC, FP32, FP64, KERNEL_KB, KERNEL_MINMAX_KB, RADIAL,  # noqa: F401
                    STAGE_IFFT_CROP, STAGE_INTERP, STAGE_NAMES, STAGE_PAD_FFT, STAGE_RADIAL,
-                   STAGE_RADIAL_ADJ, STAGE_SPREAD, UMB_STAGE_GATHER, UMB_STAGE_GRID, NufftError)
+                   STAGE_RADIAL_ADJ, STAGE_SPREAD, UMB_STAGE_GATHER, UMB_STAGE_GRID, GR_STAGE_BACKPROJECT, GR_STAGE_SPECTRA,
+                   NufftError)
 
-__all__ = ["Plan", "Batch", "Umbrella", "NufftProjector", "project", "autotune", "radial_quadrature",
+__all__ = ["Plan", "Batch", "Umbrella", "Grangeat", "NufftProjector", "project", "autotune", "radial_quadrature",
            "NufftError", "version"]
 
 
@@ -323,6 +324,72 @@ class Umbrella:
     def close(self):
         if getattr(self, "_ptr", None) is not None and self._ptr.value:
             _lib.load().nufftct_umbrella_destroy(self._ptr)
+            self._ptr = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Grangeat:
+    """Umbrella derivative-Radon values -> cone-beam projections (the Grangeat
+    step in reverse, Section 2.2.2): n_proj projections of n x n pixels from
+    n_alpha x n umbrella samples each; distances in voxels (default: the
+    Section 3.2.1 set-up scaled to an N^3 volume spanning the object)."""
+
+    def __init__(self, N, n_proj, n_alpha, n, *, J=5, scan=None, dtype=None):
+        torch = _torch()
+        self.dtype = dtype or torch.complex64
+        prec = {torch.complex64: FP32, torch.complex128: FP64}[self.dtype]
+        if scan is None:
+            so, sd, det, obj = SCAN_MM
+            scan = (N * so / obj, N * sd / obj, N * det / obj)
+        self.n_proj, self.n_alpha, self.n = int(n_proj), int(n_alpha), int(n)
+        self._ptr = C.c_void_p()
+        _lib.check(_lib.load().nufftct_grangeat_create(
+            C.byref(self._ptr), self.n_proj, self.n_alpha, self.n, float(scan[0]), float(scan[1]),
+            float(scan[2]), int(J), prec, C.c_void_p(_stream_handle())))
+
+    def project(self, u, out=None, *, stream=None):
+        torch = _torch()
+        _check_tensor(u, self.n_proj * self.n_alpha * self.n, self.dtype, "u")
+        if out is None:
+            out = torch.empty((self.n_proj, self.n, self.n), dtype=self.dtype, device=u.device)
+        _check_tensor(out, self.n_proj * self.n * self.n, self.dtype, "out")
+        _lib.check(_lib.load().nufftct_grangeat_project(self._ptr, u.data_ptr(), out.data_ptr(),
+                                                        C.c_void_p(_stream_handle(stream))))
+        return out
+
+    def stage(self, which, x, out=None, *, stream=None):
+        """"spectra" (umbrella samples -> filtered spectra, [alpha][m][proj])
+        or "backproject" (spectra -> projections)."""
+        torch = _torch()
+        n_spec = self.n_alpha * 2 * self.n * self.n_proj
+        if which == "spectra":
+            code, n_in, shape = GR_STAGE_SPECTRA, self.n_proj * self.n_alpha * self.n, \
+                (self.n_alpha, 2 * self.n, self.n_proj)
+        elif which == "backproject":
+            code, n_in, shape = GR_STAGE_BACKPROJECT, n_spec, (self.n_proj, self.n, self.n)
+        else:
+            raise ValueError(which)
+        _check_tensor(x, n_in, self.dtype, "x")
+        if out is None:
+            out = torch.empty(shape, dtype=self.dtype, device=x.device)
+        _check_tensor(out, shape[0] * shape[1] * shape[2], self.dtype, "out")
+        _lib.check(_lib.load().nufftct_grangeat_stage(self._ptr, code, x.data_ptr(), out.data_ptr(),
+                                                      C.c_void_p(_stream_handle(stream))))
+        return out
+
+    def entries(self):
+        n = C.c_int64()
+        _lib.check(_lib.load().nufftct_grangeat_info(self._ptr, C.byref(n)))
+        return n.value
+
+    def close(self):
+        if getattr(self, "_ptr", None) is not None and self._ptr.value:
+            _lib.load().nufftct_grangeat_destroy(self._ptr)
             self._ptr = C.c_void_p()
 
     def __del__(self):

@@ -15,6 +15,7 @@ DERIV_RADIAL = RADIAL | DERIV
 DETERMINISTIC = 4
 STAGE_PAD_FFT, STAGE_INTERP, STAGE_RADIAL, STAGE_RADIAL_ADJ, STAGE_SPREAD, STAGE_IFFT_CROP = range(6)
 UMB_STAGE_GRID, UMB_STAGE_GATHER = 0, 1
+GR_STAGE_SPECTRA, GR_STAGE_BACKPROJECT = 0, 1
 STAGE_NAMES = ["pad_fft", "interp", "radial", "radial_adj", "spread", "ifft_crop", "merge"]
 TIMING_MERGE = 6
 
@@ -45,6 +46,12 @@ SIGNATURES = {
     "nufftct_umbrella_grid_shape": (C.c_int, [_p, C.POINTER(_i64)]),
     "nufftct_umbrella_stage": (C.c_int, [_p, C.c_int, _p, _p, _p]),
     "nufftct_umbrella_resample": (C.c_int, [_p, _p, _p, _p]),
+    "nufftct_grangeat_create": (C.c_int, [C.POINTER(_p), _i64, _i64, _i64, C.c_double, C.c_double,
+                                          C.c_double, C.c_int, C.c_int, _p]),
+    "nufftct_grangeat_project": (C.c_int, [_p, _p, _p, _p]),
+    "nufftct_grangeat_stage": (C.c_int, [_p, C.c_int, _p, _p, _p]),
+    "nufftct_grangeat_info": (C.c_int, [_p, C.POINTER(_i64)]),
+    "nufftct_grangeat_destroy": (C.c_int, [_p]),
     "nufftct_umbrella_destroy": (C.c_int, [_p]),
     "nufftct_stage": (C.c_int, [_p, C.c_int, _p, _p, C.c_int, _p]),
     "nufftct_plan_destroy": (C.c_int, [_p]),

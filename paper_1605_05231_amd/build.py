@@ -13,9 +13,9 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libnufftct.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["plan.cpp", "host_plan.cpp", "tables.cpp", "batch.cpp", "umbrella.cpp", "k_fft_f32.hip", "k_fft_f64.hip",
-           "k_grid_f32.hip", "k_grid_f64.hip", "k_umbrella.hip", "k_resample1_f32.hip",
-           "k_resample1_f64.hip"]
+SOURCES = ["plan.cpp", "host_plan.cpp", "tables.cpp", "batch.cpp", "umbrella.cpp", "grangeat.cpp",
+           "k_fft_f32.hip", "k_fft_f64.hip", "k_grid_f32.hip", "k_grid_f64.hip", "k_umbrella.hip",
+           "k_resample1_f32.hip", "k_resample1_f64.hip", "k_grangeat_f32.hip", "k_grangeat_f64.hip"]
 
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -24,7 +24,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-I", os.path.join(ROOT, "include"), "-Wno-unused-command-line-argument"]
 HOST_ONLY = {"plan.cpp": ["-ffp-contract=off"], "host_plan.cpp": ["-ffp-contract=off"],
              "tables.cpp": ["-ffp-contract=off"],
-             "batch.cpp": [], "umbrella.cpp": []}
+             "batch.cpp": [], "umbrella.cpp": [], "grangeat.cpp": []}
 
 
 def hipcc() -> str:
