@@ -11,9 +11,10 @@
 //   k_gr_rows: the KB spreading of the n_alpha x 2n polar points onto the
 //     K x K grid (K = 2n) in gather form: the points and weights that reach
 //     each cell are the same for every projection (a CSR list made on the
-//     host), so a workgroup gathers one grid row for NK projections, reading
-//     each list entry once for all of them, then runs the inverse FFT along
-//     the row in LDS and keeps the n columns of the crop.
+//     host), so a workgroup gathers one grid row for NK projections (NK lanes
+//     per cell, reading each list entry's NK spectra as one 128-byte
+//     segment), then runs the inverse FFT along the row in LDS and keeps the
+//     n columns of the crop.
 //   k_gr_cols: the inverse FFT along the columns (NLC adjacent columns per
 //     tile), the crop to n rows, and the deapodization and de-preweighting
 //     s(m_u) s(m_v) sqrt(R^2 + u'^2 + v'^2) / R in FP64, rounded once.
@@ -33,6 +34,12 @@ constexpr int NT_COL = 512;   // column workgroups
 template <typename T>
 constexpr int nk() {  // projections per radial / row workgroup
   return sizeof(T) == 4 ? 8 : 4;
+}
+
+template <typename T, int K>
+constexpr int nk_rows() {  // projections per row workgroup: 128-byte spectra segments
+  if constexpr (sizeof(T) == 4) return K <= 512 ? 16 : 8;
+  return K <= 512 ? 8 : 4;
 }
 
 template <typename T, int K>
@@ -120,49 +127,73 @@ __global__ __launch_bounds__(NT) void k_gr_rows(const cx<T>* __restrict__ c,
                                                 const int32_t* __restrict__ off,
                                                 const int32_t* __restrict__ pt,
                                                 const T* __restrict__ w,
-                                                const cx<T>* __restrict__ tw, int n_proj) {
-  constexpr int K = 2 * NN, NK = nk<T>();
+                                                const cx<T>* __restrict__ tw, int n_proj,
+                                                int n_groups) {
+  constexpr int K = 2 * NN, NK = nk_rows<T, K>();
+  constexpr int CPP = NT / NK;  // cells per pass: NK lanes (one per projection) per cell
   __shared__ cx<T> buf[fft::tile_elems<true, K, NK>()];
   __shared__ cx<T> twl[K];
   const int tid = threadIdx.x;
   for (int q = tid; q < K; q += NT) twl[q] = tw[q];
-  const int k0 = blockIdx.x * NK;
-  const int kv = blockIdx.y;
+  // workgroups go round-robin over the XCDs: give each XCD a contiguous run of
+  // rows of one projection group, so the rows sharing polar points (every
+  // point reaches J rows) meet in one L2
+  int b = blockIdx.x;
+  const int nb = gridDim.x;
+  if ((nb & (NUFFTCT_NUM_XCD - 1)) == 0) b = (b % NUFFTCT_NUM_XCD) * (nb / NUFFTCT_NUM_XCD) + b / NUFFTCT_NUM_XCD;
+  const int grp = b / K, kv = b % K;
+  if (grp >= n_groups) return;
+  const int k0 = grp * NK;
   const int nk_here = n_proj - k0 < NK ? n_proj - k0 : NK;
-  for (int ku = tid; ku < K; ku += NT) {
-    const int cell = kv * K + ku;
-    cx<T> acc[NK];
+  // lane q of a cell's NK lanes gathers projection k0 + q: the lanes read the
+  // NK consecutive spectra of a list entry as one segment
+  const int q = tid % NK;
+  const bool live = q < nk_here;
+  for (int cu0 = 0; cu0 < K; cu0 += CPP) {
+    const int ku = cu0 + tid / NK;
+    cx<T> acc = {0, 0};
+    if (ku < K) {
+      const int cell = kv * K + ku;
+      const int e1 = off[cell + 1];
+      const cx<T>* src = c + k0 + q;
+      int e = off[cell];
+      // UF entries at a time: their list reads, then their spectra reads, are
+      // in flight together (one at a time the loop waits on each pair of
+      // dependent loads); the sums keep the list order
+      constexpr int UF = 4;
+      for (; e + UF <= e1; e += UF) {
+        int p[UF];
+        T we[UF];
 #pragma unroll
-    for (int q = 0; q < NK; ++q) acc[q] = cx<T>{0, 0};
-    const int e1 = off[cell + 1];
-    for (int e = off[cell]; e < e1; ++e) {
-      const T we = w[e];
-      const cx<T>* src = c + (int64_t)pt[e] * n_proj + k0;
-      if (nk_here == NK) {
-#pragma unroll
-        for (int q = 0; q < NK; ++q) {
-          const cx<T> v = src[q];
-          acc[q].x += we * v.x;
-          acc[q].y += we * v.y;
+        for (int r = 0; r < UF; ++r) {
+          p[r] = pt[e + r];
+          we[r] = w[e + r];
         }
-      } else {
-        for (int q = 0; q < nk_here; ++q) {
-          const cx<T> v = src[q];
-          acc[q].x += we * v.x;
-          acc[q].y += we * v.y;
+        cx<T> v[UF];
+#pragma unroll
+        for (int r = 0; r < UF; ++r) v[r] = live ? src[(int64_t)p[r] * n_proj] : cx<T>{0, 0};
+#pragma unroll
+        for (int r = 0; r < UF; ++r) {
+          acc.x += we[r] * v[r].x;
+          acc.y += we[r] * v[r].y;
         }
       }
+      for (; e < e1; ++e) {
+        const T we = w[e];
+        const cx<T> v = live ? src[(int64_t)pt[e] * n_proj] : cx<T>{0, 0};
+        acc.x += we * v.x;
+        acc.y += we * v.y;
+      }
+      buf[fft::addr<true, K, NK>(q, ku)] = acc;
     }
-#pragma unroll
-    for (int q = 0; q < NK; ++q) buf[fft::addr<true, K, NK>(q, ku)] = acc[q];
   }
   __syncthreads();
   fft::run<T, K, NK, NT, true, +1>(buf, twl, tid);
   for (int idx = tid; idx < NK * NN; idx += NT) {
-    const int q = idx / NN, a = idx % NN;
-    if (q < nk_here) {
+    const int qq = idx / NN, a = idx % NN;
+    if (qq < nk_here) {
       const int col = a - NN / 2 < 0 ? a - NN / 2 + K : a - NN / 2;
-      rows[((int64_t)(k0 + q) * K + kv) * NN + a] = buf[fft::addr<true, K, NK>(q, col)];
+      rows[((int64_t)(k0 + qq) * K + kv) * NN + a] = buf[fft::addr<true, K, NK>(qq, col)];
     }
   }
 }
@@ -225,14 +256,15 @@ hipError_t radial(const nufftct_grangeat& g, const void* umb, void* c, hipStream
 
 template <typename T>
 hipError_t backproject(const nufftct_grangeat& g, const void* c, void* x, hipStream_t st) {
-  constexpr int NK = nk<T>();
   switch (g.n) {
 #define CASE(NN)                                                                                \
   case NN: {                                                                                    \
     constexpr int NL = nlc<T, 2 * NN>();                                                        \
-    hipLaunchKernelGGL((k_gr_rows<T, NN>), dim3((unsigned)((g.n_proj + NK - 1) / NK), 2 * NN), \
-                       dim3(NT), 0, st, (const cx<T>*)c, (cx<T>*)g.d_rows, g.d_off, g.d_pt,     \
-                       (const T*)g.d_w, (const cx<T>*)g.d_tw, g.n_proj);                        \
+    constexpr int NKR = nk_rows<T, 2 * NN>();                                                   \
+    const int ngr = (g.n_proj + NKR - 1) / NKR;                                                 \
+    hipLaunchKernelGGL((k_gr_rows<T, NN>), dim3((unsigned)(ngr * 2 * NN)), dim3(NT), 0, st,     \
+                       (const cx<T>*)c, (cx<T>*)g.d_rows, g.d_off, g.d_pt, (const T*)g.d_w,     \
+                       (const cx<T>*)g.d_tw, g.n_proj, ngr);                                    \
     hipError_t e = hipGetLastError();                                                           \
     if (e != hipSuccess) return e;                                                              \
     hipLaunchKernelGGL((k_gr_cols<T, NN>), dim3((unsigned)((NN + NL - 1) / NL), g.n_proj),      \

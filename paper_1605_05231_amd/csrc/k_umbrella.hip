@@ -2,8 +2,10 @@
 // umbrella sample.  The plane through the source that meets the detector in
 // the sample's line is built in FP64, mapped to (phi, theta, rho) index
 // coordinates of the radial grid, and the J^3 taps around it are gathered
-// with the normalised KB-windowed sinc weights, evaluated directly in FP64.
-// phi wraps; theta and rho taps off the grid contribute nothing.
+// with the normalised KB-windowed sinc weights: per-tap polynomials in
+// z = 2 frac - 1 fitted on the host (Chebyshev interpolation, degree 15 FP32 /
+// 23 FP64, used when the fit meets 1e-7 / 1e-13), else evaluated directly in
+// FP64.  phi wraps; theta and rho taps off the grid contribute nothing.
 #include "cx.h"
 #include "umbrella.h"
 
@@ -47,9 +49,27 @@ __device__ __forceinline__ void taps(double t, double beta, double inv_i0b, int&
   for (int a = 0; a < J; ++a) w[a] = (T)(wd[a] * inv);
 }
 
-template <typename T, int J>
+// The same from the per-tap polynomials.
+template <typename T, int J, int DEG>
+__device__ __forceinline__ void taps_poly(double t, const TapPoly<T, DEG>& P, int& k0,
+                                          T (&w)[J]) {
+  const double tj = t - 0.5 * (double)J;
+  const double f = floor(tj);
+  k0 = (int)f;
+  const T z = (T)(2.0 * (tj - f) - 1.0);
+#pragma unroll
+  for (int a = 0; a < J; ++a) {
+    T acc = P.c[a][DEG];
+#pragma unroll
+    for (int d = DEG - 1; d >= 0; --d) acc = acc * z + P.c[a][d];
+    w[a] = acc;
+  }
+}
+
+template <typename T, int J, int DEG, bool POLY>
 __global__ __launch_bounds__(NT) void k_umbrella(const cx<T>* __restrict__ D,
-                                                 cx<T>* __restrict__ out, UmbrellaGeom g) {
+                                                 cx<T>* __restrict__ out, UmbrellaGeom g,
+                                                 TapPoly<T, DEG> P) {
 #pragma clang fp contract(off)
   const int64_t total = (int64_t)g.n_proj * g.n_alpha * g.n_t;
   const int64_t p = (int64_t)blockIdx.x * NT + threadIdx.x;
@@ -58,9 +78,15 @@ __global__ __launch_bounds__(NT) void k_umbrella(const cx<T>* __restrict__ D,
   umbrella_coords(g, p, tp, tt, tr);
   int kp, kt, kr;
   T wp[J], wt[J], wr[J];
-  taps<T, J>(tp, g.beta, g.inv_i0beta, kp, wp);
-  taps<T, J>(tt, g.beta, g.inv_i0beta, kt, wt);
-  taps<T, J>(tr, g.beta, g.inv_i0beta, kr, wr);
+  if constexpr (POLY) {
+    taps_poly<T, J, DEG>(tp, P, kp, wp);
+    taps_poly<T, J, DEG>(tt, P, kt, wt);
+    taps_poly<T, J, DEG>(tr, P, kr, wr);
+  } else {
+    taps<T, J>(tp, g.beta, g.inv_i0beta, kp, wp);
+    taps<T, J>(tt, g.beta, g.inv_i0beta, kt, wt);
+    taps<T, J>(tr, g.beta, g.inv_i0beta, kr, wr);
+  }
   cx<T> acc = {0, 0};
 #pragma unroll
   for (int a = 0; a < J; ++a) {
@@ -90,12 +116,30 @@ __global__ __launch_bounds__(NT) void k_umbrella(const cx<T>* __restrict__ D,
   out[p] = acc;
 }
 
+template <typename T>
+struct PolyOf;
+template <>
+struct PolyOf<float> {
+  static constexpr int DEG = NUFFTCT_UMB_DEG_F32;
+  static const TapPoly<float, DEG>& get(const nufftct_umbrella& u) { return u.tp32; }
+};
+template <>
+struct PolyOf<double> {
+  static constexpr int DEG = NUFFTCT_UMB_DEG_F64;
+  static const TapPoly<double, DEG>& get(const nufftct_umbrella& u) { return u.tp64; }
+};
+
 template <typename T, int J>
 hipError_t launch(const nufftct_umbrella& u, const void* in, void* out, hipStream_t st) {
+  constexpr int DEG = PolyOf<T>::DEG;
   const int64_t total = (int64_t)u.g.n_proj * u.g.n_alpha * u.g.n_t;
   const dim3 grd((unsigned)((total + NT - 1) / NT));
-  hipLaunchKernelGGL((k_umbrella<T, J>), grd, dim3(NT), 0, st, (const cx<T>*)in, (cx<T>*)out,
-                     u.g);
+  if (u.poly)
+    hipLaunchKernelGGL((k_umbrella<T, J, DEG, true>), grd, dim3(NT), 0, st, (const cx<T>*)in,
+                       (cx<T>*)out, u.g, PolyOf<T>::get(u));
+  else
+    hipLaunchKernelGGL((k_umbrella<T, J, DEG, false>), grd, dim3(NT), 0, st, (const cx<T>*)in,
+                       (cx<T>*)out, u.g, PolyOf<T>::get(u));
   return hipGetLastError();
 }
 

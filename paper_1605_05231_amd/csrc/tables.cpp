@@ -174,6 +174,43 @@ long double fit_kb(int J, double beta, int deg, std::vector<long double>& re) {
   return err;
 }
 
+long double fit_window_sinc(int J, double beta, int deg, std::vector<long double>& re) {
+  re.assign((size_t)J * (deg + 1), 0.0L);
+  // w_a(frac) = sinc(u_a) I0(beta sqrt(1 - (2 u_a / J)^2)) / sum_b (same at u_b),
+  // u_a = J/2 - 1 - a + frac: the normalised window of the radial resampling
+  auto weights = [&](long double frac, std::vector<long double>& wv) {
+    long double sum = 0;
+    for (int a = 0; a < J; ++a) {
+      const long double u = (long double)J / 2 - 1 - a + frac;
+      const long double sc = u == 0 ? 1.0L : std::sin(PI_L * u) / (PI_L * u);
+      const long double r = 1.0L - (2.0L * u / J) * (2.0L * u / J);
+      const long double ps = r >= 0 ? bessel_i0((long double)beta * std::sqrt(r)) : 0.0L;
+      wv[a] = sc * ps;
+      sum += wv[a];
+    }
+    for (int a = 0; a < J; ++a) wv[a] /= sum;
+  };
+  const int n = deg + 1;
+  std::vector<long double> wv(J);
+  std::vector<std::vector<long double>> fv(J, std::vector<long double>(n));
+  for (int k = 0; k < n; ++k) {
+    weights(0.5L * (cheb_node(k, n) + 1.0L), wv);
+    for (int a = 0; a < J; ++a) fv[a][k] = wv[a];
+  }
+  for (int a = 0; a < J; ++a) {
+    auto c = cheb_from_values(fv[a]);
+    for (int k = 0; k <= deg; ++k) re[(size_t)a * (deg + 1) + k] = c[k];
+  }
+  long double err = 0;
+  for (int i = 0; i <= 400; ++i) {
+    const long double z = -1.0L + 2.0L * i / 400;
+    weights(0.5L * (z + 1.0L), wv);
+    for (int a = 0; a < J; ++a)
+      err = std::max(err, std::fabs(horner(&re[(size_t)a * (deg + 1)], deg, z) - wv[a]));
+  }
+  return err;
+}
+
 long double fit_minmax(const MinMax& mm, int deg, std::vector<long double>& re,
                        std::vector<long double>& im) {
   const int J = mm.J;

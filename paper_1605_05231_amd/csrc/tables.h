@@ -45,6 +45,9 @@ struct MinMax {
 // monomial basis).  re/im: J x (deg+1) coefficients.  Returns the maximum
 // absolute error measured on a fine grid in long double.
 long double fit_kb(int J, double beta, int deg, std::vector<long double>& re);
+// The same for the normalised KB-windowed sinc weights of the radial ->
+// umbrella resampling: w_a = sinc(u_a) psi(u_a) / sum_b sinc(u_b) psi(u_b).
+long double fit_window_sinc(int J, double beta, int deg, std::vector<long double>& re);
 long double fit_minmax(const MinMax& mm, int deg, std::vector<long double>& re,
                        std::vector<long double>& im);
 

@@ -125,8 +125,23 @@ int nufftct_umbrella_create(nufftct_umbrella** out, int64_t n_proj, int64_t n_al
                             int64_t n_phi, int64_t n_theta, double theta0, double dtheta,
                             int64_t n_r, int J, int precision, void* stream) {
   (void)stream;
-  return make_umbrella(out, n_proj, n_alpha, n_t, source_radius, source_detector, detector_side,
-                       n_phi, n_theta, theta0, dtheta, n_r, J, precision);
+  int rc = make_umbrella(out, n_proj, n_alpha, n_t, source_radius, source_detector, detector_side,
+                         n_phi, n_theta, theta0, dtheta, n_r, J, precision);
+  if (rc) return rc;
+  // per-tap polynomial weights (the same function the kernel would evaluate)
+  nufftct_umbrella* u = *out;
+  const bool f32 = precision == NUFFTCT_FP32;
+  const int deg = f32 ? NUFFTCT_UMB_DEG_F32 : NUFFTCT_UMB_DEG_F64;
+  std::vector<long double> re;
+  const long double err = tables::fit_window_sinc(J, u->g.beta, deg, re);
+  u->poly = err <= (f32 ? 1e-7L : 1e-13L);
+  for (int a = 0; a < J; ++a)
+    for (int k = 0; k <= deg; ++k) {
+      const long double c = re[(size_t)a * (deg + 1) + k];
+      if (f32) u->tp32.c[a][k] = (float)c;
+      else u->tp64.c[a][k] = (double)c;
+    }
+  return NUFFTCT_OK;
 }
 
 int nufftct_umbrella1_create(nufftct_umbrella** out, int64_t n_proj, int64_t n_alpha,

@@ -17,10 +17,24 @@ struct UmbrellaGeom {
   double beta, inv_i0beta;   // Kaiser-Bessel window of the method-2 weights
 };
 
+// Method 2: per-tap polynomial fits (in z = 2 frac - 1) of the normalised
+// windowed-sinc weights, by precision.
+#define NUFFTCT_UMB_DEG_F32 15
+#define NUFFTCT_UMB_DEG_F64 23
+template <typename T, int DEG>
+struct TapPoly {
+  T c[NUFFTCT_MAXJ][DEG + 1];
+};
+
 struct nufftct_umbrella {
   UmbrellaGeom g{};
   int J = 0, precision = 0;
   int method = 2;
+  // method 2: weights from the fits when they meet the precision's bound
+  // (1e-7 FP32, 1e-13 FP64), else evaluated directly in FP64
+  bool poly = false;
+  TapPoly<float, NUFFTCT_UMB_DEG_F32> tp32{};
+  TapPoly<double, NUFFTCT_UMB_DEG_F64> tp64{};
   // method 1 (eq 2.11): oversampled grid K_d = 2 N_d per axis [phi][theta][rho]
   int64_t K[3] = {0, 0, 0};
   void* d_tw_n[3] = {nullptr, nullptr, nullptr};  // twiddles of length N_d (plan precision)
