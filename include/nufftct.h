@@ -399,19 +399,28 @@ int nufftct_grangeat_destroy(nufftct_grangeat* g);
  * Batch of independent volumes of uneven size (each with its own radial
  * direction set).  The batch owns one plan per volume (created with the
  * given parameters; J, kernel, beta and precision are shared), each with its
- * own workspace, so the volumes are independent: they are dealt to up to four
- * worker streams (longest-processing-time order by estimated cost) that fork
- * from the caller's stream and join back into it, so that small volumes run
- * side by side.  Arrays are HOST arrays of length nvol; dirs[b] is a HOST
- * pointer to n_lines[b] x 3 doubles.  Errors: EINVAL (a null array, nvol < 1,
- * or any volume's plan parameters, reported with its index), ENOMEM, EHIP.
+ * own workspace, so the volumes are independent.  With Kaiser-Bessel weights
+ * and the radial stage, volumes of equal N, K and n_r on grids below 192^3
+ * are grouped into units that run every stage as one launch across the
+ * unit's volumes (FFT and radial passes over up to 64 volumes at once, the
+ * point stages over all of them); larger volumes, and every volume of a
+ * min-max batch, run their own plan's kernels.  The units are dealt to up
+ * to four worker streams (longest-processing-time order by estimated cost)
+ * that fork from the caller's stream and join back into it, so that units
+ * run side by side.  Results equal the volumes' single plans bit for bit.
+ * Arrays are HOST arrays of length nvol; dirs[b] is a HOST pointer to
+ * n_lines[b] x 3 doubles.  Create also allocates the units' small device
+ * tables.  Errors: EINVAL (a null array, nvol < 1, or any volume's plan
+ * parameters, reported with its index), EUNSUPPORTED (a unit too large for
+ * one launch per stage), ENOMEM, EHIP.
  */
 int nufftct_batch_create(nufftct_batch** out, int nvol, const int64_t* N, const int64_t* K,
                          int J, int kernel, double beta, int precision,
                          const double* const* dirs, const int64_t* n_lines,
                          const int64_t* n_r, void* stream);
 
-/* vols[b], outs[b]: device pointers per volume (sizes as for that volume's plan). */
+/* vols[b], outs[b]: device pointers per volume (sizes as for that volume's plan);
+ * flags as for nufftct_forward / nufftct_adjoint (DETERMINISTIC included). */
 int nufftct_batch_forward(nufftct_batch* batch, const void* const* vols, void* const* outs,
                           int flags, void* stream);
 int nufftct_batch_adjoint(nufftct_batch* batch, const void* const* ins, void* const* vols,

@@ -446,10 +446,11 @@ class Batch:
                                                      C.c_void_p(_stream_handle(stream))))
         return outs
 
-    def adjoint(self, ys, outs, *, deriv=True, stream=None):
+    def adjoint(self, ys, outs, *, deriv=True, deterministic=False, stream=None):
         a = self._ptrs(ys, self.Ms, "y")
         b = self._ptrs(outs, [n ** 3 for n in self.Ns], "out")
-        _lib.check(_lib.load().nufftct_batch_adjoint(self._ptr, a, b, RADIAL | (DERIV if deriv else 0),
+        flags = RADIAL | (DERIV if deriv else 0) | (DETERMINISTIC if deterministic else 0)
+        _lib.check(_lib.load().nufftct_batch_adjoint(self._ptr, a, b, flags,
                                                      C.c_void_p(_stream_handle(stream))))
         return outs
 

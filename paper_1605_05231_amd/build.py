@@ -15,7 +15,8 @@ BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["plan.cpp", "host_plan.cpp", "tables.cpp", "batch.cpp", "umbrella.cpp", "grangeat.cpp",
            "k_fft_f32.hip", "k_fft_f64.hip", "k_grid_f32.hip", "k_grid_f64.hip", "k_umbrella.hip",
-           "k_resample1_f32.hip", "k_resample1_f64.hip", "k_grangeat_f32.hip", "k_grangeat_f64.hip"]
+           "k_resample1_f32.hip", "k_resample1_f64.hip", "k_grangeat_f32.hip", "k_grangeat_f64.hip",
+           "k_batch_f32.hip", "k_batch_f64.hip"]
 
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -50,11 +50,13 @@ __device__ __forceinline__ int wrap_of(int m, int K) { return m >= 0 ? m : m + K
 
 // ---------------------------------------------------------------------------
 // forward pass x (deapodize + pad + FFT along the contiguous axis)
+// (each kernel below is a device body taking its block indices, wrapped by a
+// one-plan kernel here and by the batch kernels of k_batch_impl.h)
 template <typename T, int L>
-__global__ __launch_bounds__(NT) void k_pad_fft_x(const cx<T>* __restrict__ vol,
-                                                  cx<T>* __restrict__ grid,
-                                                  const double* __restrict__ s,
-                                                  const cx<T>* __restrict__ tw, int N) {
+__device__ __forceinline__ void pad_fft_x_body(int64_t bx, const cx<T>* __restrict__ vol,
+                                               cx<T>* __restrict__ grid,
+                                               const double* __restrict__ s,
+                                               const cx<T>* __restrict__ tw, int N) {
   constexpr int NL = nl_line<T, L>();
   constexpr int K = L;
   __shared__ cx<T> buf[fft::tile_elems<true, L, NL>()];
@@ -63,7 +65,7 @@ __global__ __launch_bounds__(NT) void k_pad_fft_x(const cx<T>* __restrict__ vol,
   const cx<T>* twp = twl;
   const int tid = threadIdx.x;
   const int64_t nlines = (int64_t)N * N;
-  const int64_t line0 = (int64_t)blockIdx.x * NL;
+  const int64_t line0 = bx * NL;
   const int h = N / 2;
   stage::tile<T, NL * L, NT>(
       tid,
@@ -96,6 +98,14 @@ __global__ __launch_bounds__(NT) void k_pad_fft_x(const cx<T>* __restrict__ vol,
   }
 }
 
+template <typename T, int L>
+__global__ __launch_bounds__(NT) void k_pad_fft_x(const cx<T>* __restrict__ vol,
+                                                  cx<T>* __restrict__ grid,
+                                                  const double* __restrict__ s,
+                                                  const cx<T>* __restrict__ tw, int N) {
+  pad_fft_x_body<T, L>(blockIdx.x, vol, grid, s, tw, N);
+}
+
 // ---------------------------------------------------------------------------
 // strided pass (axis 1 or 0): NLC adjacent columns per workgroup.
 //   outer index o: pruned -> plane (o - N/2) mod K for o < N; else o < K
@@ -109,12 +119,12 @@ __global__ __launch_bounds__(NT) void k_pad_fft_x(const cx<T>* __restrict__ vol,
 // ball = 2: load only such rows, the rest being zero (adjoint).  outer_in_ball
 // says whether the outer index is a transformed (centred) axis.
 template <typename T, int L, int S>
-__global__ __launch_bounds__(NTS) void k_fft_strided(cx<T>* __restrict__ grid,
-                                                    const cx<T>* __restrict__ tw, int N,
-                                                    int64_t row_stride, int64_t outer_stride,
-                                                    int outer_pruned, int load_pruned,
-                                                    int store_pruned, double r2, int ball,
-                                                    int outer_in_ball) {
+__device__ __forceinline__ void fft_strided_body(int bx, int by, int gx, cx<T>* __restrict__ grid,
+                                                 const cx<T>* __restrict__ tw, int N,
+                                                 int64_t row_stride, int64_t outer_stride,
+                                                 int outer_pruned, int load_pruned,
+                                                 int store_pruned, double r2, int ball,
+                                                 int outer_in_ball) {
   constexpr int NL = nl_col<T, L>();
   constexpr int K = L;
   __shared__ cx<T> buf[fft::tile_elems<false, L, NL>()];
@@ -125,14 +135,14 @@ __global__ __launch_bounds__(NTS) void k_fft_strided(cx<T>* __restrict__ grid,
   const cx<T>* twp = twl;
   const int tid = threadIdx.x;
   const int h = N / 2;
-  const int o = blockIdx.y;
+  const int o = by;
   const int qo = outer_pruned ? wrap_of(o - h, K) : o;
   // workgroups go round-robin over the 8 XCDs: give each XCD a contiguous
   // run of column groups, so that the groups sharing a cache line of a row
   // meet in one L2
-  int cg = blockIdx.x;
-  if ((gridDim.x & (NUFFTCT_NUM_XCD - 1)) == 0)
-    cg = (cg % NUFFTCT_NUM_XCD) * (gridDim.x / NUFFTCT_NUM_XCD) + cg / NUFFTCT_NUM_XCD;
+  int cg = bx;
+  if ((gx & (NUFFTCT_NUM_XCD - 1)) == 0)
+    cg = (cg % NUFFTCT_NUM_XCD) * (gx / NUFFTCT_NUM_XCD) + cg / NUFFTCT_NUM_XCD;
   const int col0 = cg * NL;
   cx<T>* base = grid + (int64_t)qo * outer_stride + col0;
   // squared distance of this block's nearest column from the ball's axis
@@ -182,13 +192,25 @@ __global__ __launch_bounds__(NTS) void k_fft_strided(cx<T>* __restrict__ grid,
   }
 }
 
+template <typename T, int L, int S>
+__global__ __launch_bounds__(NTS) void k_fft_strided(cx<T>* __restrict__ grid,
+                                                    const cx<T>* __restrict__ tw, int N,
+                                                    int64_t row_stride, int64_t outer_stride,
+                                                    int outer_pruned, int load_pruned,
+                                                    int store_pruned, double r2, int ball,
+                                                    int outer_in_ball) {
+  fft_strided_body<T, L, S>(blockIdx.x, blockIdx.y, gridDim.x, grid, tw, N, row_stride,
+                            outer_stride, outer_pruned, load_pruned, store_pruned, r2, ball,
+                            outer_in_ball);
+}
+
 // ---------------------------------------------------------------------------
 // adjoint pass x (inverse FFT along the contiguous axis + crop + deapodize)
 template <typename T, int L>
-__global__ __launch_bounds__(NT) void k_ifft_crop_x(const cx<T>* __restrict__ grid,
-                                                    cx<T>* __restrict__ vol,
-                                                    const double* __restrict__ s,
-                                                    const cx<T>* __restrict__ tw, int N) {
+__device__ __forceinline__ void ifft_crop_x_body(int64_t bx, const cx<T>* __restrict__ grid,
+                                                 cx<T>* __restrict__ vol,
+                                                 const double* __restrict__ s,
+                                                 const cx<T>* __restrict__ tw, int N) {
   constexpr int NL = nl_line<T, L>();
   constexpr int K = L;
   __shared__ cx<T> buf[fft::tile_elems<true, L, NL>()];
@@ -197,7 +219,7 @@ __global__ __launch_bounds__(NT) void k_ifft_crop_x(const cx<T>* __restrict__ gr
   const cx<T>* twp = twl;
   const int tid = threadIdx.x;
   const int64_t nlines = (int64_t)N * N;
-  const int64_t line0 = (int64_t)blockIdx.x * NL;
+  const int64_t line0 = bx * NL;
   const int h = N / 2;
   stage::tile<T, NL * L, NT>(
       tid,
@@ -232,25 +254,33 @@ __global__ __launch_bounds__(NT) void k_ifft_crop_x(const cx<T>* __restrict__ gr
   }
 }
 
+template <typename T, int L>
+__global__ __launch_bounds__(NT) void k_ifft_crop_x(const cx<T>* __restrict__ grid,
+                                                    cx<T>* __restrict__ vol,
+                                                    const double* __restrict__ s,
+                                                    const cx<T>* __restrict__ tw, int N) {
+  ifft_crop_x_body<T, L>(blockIdx.x, grid, vol, s, tw, N);
+}
+
 // ---------------------------------------------------------------------------
 // radial stage (eq 2.17-2.18): per line of L = N_r samples
 //   forward: D_j = (1/L) sum_c f_c G_c exp(+i r_c rho_j)
 //          = (-1)^j (-1)^(L/2) / L * IDFT[(-1)^c f_c G_c]_j
 //   adjoint: G~_c = conj(f_c) (-1)^c (-1)^(L/2) / L * DFT[(-1)^j d_j]_c
 template <typename T, int L, bool ADJ>
-__global__ __launch_bounds__(NT) void k_radial(const cx<T>* __restrict__ in,
-                                               cx<T>* __restrict__ out,
-                                               const cx<T>* __restrict__ tw, int64_t nlines,
-                                               int deriv, double dr,
-                                               const double* __restrict__ line_w,
-                                               double w_scale) {
+__device__ __forceinline__ void radial_body(int64_t bx, const cx<T>* __restrict__ in,
+                                            cx<T>* __restrict__ out,
+                                            const cx<T>* __restrict__ tw, int64_t nlines,
+                                            int deriv, double dr,
+                                            const double* __restrict__ line_w,
+                                            double w_scale) {
   constexpr int NL = nl_line<T, L>();
   __shared__ cx<T> buf[fft::tile_elems<true, L, NL>()];
   __shared__ cx<T> twl[L];
   for (int i = threadIdx.x; i < L; i += NT) twl[i] = tw[i];
   const cx<T>* twp = twl;
   const int tid = threadIdx.x;
-  const int64_t line0 = (int64_t)blockIdx.x * NL;
+  const int64_t line0 = bx * NL;
   const T post = (T)(((L / 2) & 1 ? -1.0 : 1.0) / (double)L);
   stage::tile<T, NL * L, NT>(
       tid,
@@ -288,6 +318,16 @@ __global__ __launch_bounds__(NT) void k_radial(const cx<T>* __restrict__ in,
       out[gl * L + e] = v;
     }
   }
+}
+
+template <typename T, int L, bool ADJ>
+__global__ __launch_bounds__(NT) void k_radial(const cx<T>* __restrict__ in,
+                                               cx<T>* __restrict__ out,
+                                               const cx<T>* __restrict__ tw, int64_t nlines,
+                                               int deriv, double dr,
+                                               const double* __restrict__ line_w,
+                                               double w_scale) {
+  radial_body<T, L, ADJ>(blockIdx.x, in, out, tw, nlines, deriv, dr, line_w, w_scale);
 }
 
 #define KFFT_SIZES(X) \

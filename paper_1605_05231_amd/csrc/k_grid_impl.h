@@ -297,20 +297,21 @@ __host__ __device__ inline int part_offset(int q0, int q1, int q2, int tile, int
 }
 
 // ---------------------------------------------------------------------------
+// (the kernels below are device bodies taking their block index, wrapped by
+// one-plan kernels here and by the batch kernels of k_batch_impl.h)
 template <typename T, int J, int TILE, bool CW, int DEG>
-__global__ __launch_bounds__(GridCfg<T>::NT_INTERP)
-__attribute__((amdgpu_waves_per_eu(GridCfg<T>::INTERP_WAVES))) void k_interp(const cx<T>* __restrict__ grid,
-                                               cx<T>* __restrict__ out,
-                                               const int32_t* __restrict__ perm,
-                                               const TileTask* __restrict__ tasks,
-                                               XcdSplit xs, PointGeom g,
-                                               int nb, WeightPoly<T, DEG> P) {
+__device__ __forceinline__ void interp_body(int64_t bx, const cx<T>* __restrict__ grid,
+                                            cx<T>* __restrict__ out,
+                                            const int32_t* __restrict__ perm,
+                                            const TileTask* __restrict__ tasks,
+                                            const XcdSplit& xs, const PointGeom& g, int nb,
+                                            const WeightPoly<T, DEG>& P) {
   constexpr int NT_INTERP = GridCfg<T>::NT_INTERP;
   constexpr int S = TILE + J - 1;
   constexpr int S2 = interp_pitch<T>(S);
   __shared__ float4 tile_mem[(S * S * S2 * (int)sizeof(cx<T>) + 15) / 16];
   cx<T>* tile = reinterpret_cast<cx<T>*>(tile_mem);
-  const int64_t task_id = xcd_task(blockIdx.x, xs);
+  const int64_t task_id = xcd_task(bx, xs);
   if (task_id < 0) return;
   const TileTask tk = tasks[task_id];
   const int K = g.K;
@@ -392,6 +393,17 @@ __attribute__((amdgpu_waves_per_eu(GridCfg<T>::INTERP_WAVES))) void k_interp(con
                                        w1i, w2r, w2i);
     out[p] = acc;
   }
+}
+
+template <typename T, int J, int TILE, bool CW, int DEG>
+__global__ __launch_bounds__(GridCfg<T>::NT_INTERP)
+__attribute__((amdgpu_waves_per_eu(GridCfg<T>::INTERP_WAVES))) void k_interp(const cx<T>* __restrict__ grid,
+                                               cx<T>* __restrict__ out,
+                                               const int32_t* __restrict__ perm,
+                                               const TileTask* __restrict__ tasks,
+                                               XcdSplit xs, PointGeom g,
+                                               int nb, WeightPoly<T, DEG> P) {
+  interp_body<T, J, TILE, CW, DEG>(blockIdx.x, grid, out, perm, tasks, xs, g, nb, P);
 }
 
 // One contribution u (already on the fixed-point scale when FIXED) to halo
@@ -1029,17 +1041,18 @@ __global__ __launch_bounds__(NT_BOUND) void k_spread_bound(float* __restrict__ b
 // (mostly single) partial loads independently.  With the block layout of the
 // partials, the cells of a row read consecutive words of each block.
 template <typename T, int TILE>
-__global__ __launch_bounds__(TILE * TILE * TILE < 1024 ? TILE * TILE * TILE : 1024) void k_merge(
-    const cx<T>* __restrict__ partials, const int32_t* __restrict__ bin_tasks,
-    const int32_t* __restrict__ order, cx<T>* __restrict__ grid, int nb, int K, int R, double r2,
-    int32_t* __restrict__ mlist) {
+__device__ __forceinline__ void merge_body(int bx, const cx<T>* __restrict__ partials,
+                                           const int32_t* __restrict__ bin_tasks,
+                                           const int32_t* __restrict__ order,
+                                           cx<T>* __restrict__ grid, int nb, int K, int R,
+                                           double r2, int32_t* __restrict__ mlist) {
   // the spreading's list of multi-class tasks has been consumed: empty it
-  if (mlist && blockIdx.x == 0 && threadIdx.x == 0) mlist[0] = 0;
+  if (mlist && bx == 0 && threadIdx.x == 0) mlist[0] = 0;
   constexpr int TT = TILE * TILE * TILE;
   constexpr int NTM = TT < 1024 ? TT : 1024;
   constexpr int PER = TT / NTM;
   const int64_t PS = part_stride(TILE, R);
-  const int tile = order[blockIdx.x];
+  const int tile = order[bx];
   const int t2 = tile % nb, t1 = (tile / nb) % nb, t0 = tile / (nb * nb);
   {
     // tiles wholly outside the ball holding every tap are never read
@@ -1099,25 +1112,32 @@ __global__ __launch_bounds__(TILE * TILE * TILE < 1024 ? TILE * TILE * TILE : 10
   }
 }
 
+template <typename T, int TILE>
+__global__ __launch_bounds__(TILE * TILE * TILE < 1024 ? TILE * TILE * TILE : 1024) void k_merge(
+    const cx<T>* __restrict__ partials, const int32_t* __restrict__ bin_tasks,
+    const int32_t* __restrict__ order, cx<T>* __restrict__ grid, int nb, int K, int R, double r2,
+    int32_t* __restrict__ mlist) {
+  merge_body<T, TILE>(blockIdx.x, partials, bin_tasks, order, grid, nb, K, R, r2, mlist);
+}
+
 // FP32 merge with C adjacent cells (C = 2 or 4; i2 a multiple of C) per
 // thread: the blocks whose rows are TILE long are read and the grid written
 // in 16-byte pairs (part_base offsets and the per-task stride are even), the
 // short-row blocks one value at a time; the per-cell summation order is the
 // one of k_merge.
 template <int TILE, int C>
-__global__ __launch_bounds__(1024) void k_merge_pairs(const cx<float>* __restrict__ partials,
-                                                      const int32_t* __restrict__ bin_tasks,
-                                                      const int32_t* __restrict__ order,
-                                                      cx<float>* __restrict__ grid, int nb, int K,
-                                                      int R, double r2,
-                                                      int32_t* __restrict__ mlist) {
+__device__ __forceinline__ void merge_pairs_body(int bx, const cx<float>* __restrict__ partials,
+                                                 const int32_t* __restrict__ bin_tasks,
+                                                 const int32_t* __restrict__ order,
+                                                 cx<float>* __restrict__ grid, int nb, int K,
+                                                 int R, double r2, int32_t* __restrict__ mlist) {
   // the spreading's list of multi-class tasks has been consumed: empty it
-  if (mlist && blockIdx.x == 0 && threadIdx.x == 0) mlist[0] = 0;
+  if (mlist && bx == 0 && threadIdx.x == 0) mlist[0] = 0;
   constexpr int TTC = TILE * TILE * TILE / C;
   constexpr int NTM = TTC < 1024 ? TTC : 1024;
   constexpr int PER = TTC / NTM;
   const int64_t PS = part_stride(TILE, R);
-  const int tile = order[blockIdx.x];
+  const int tile = order[bx];
   const int t2 = tile % nb, t1 = (tile / nb) % nb, t0 = tile / (nb * nb);
   {
     double d2 = 0.0;
@@ -1199,6 +1219,16 @@ __global__ __launch_bounds__(1024) void k_merge_pairs(const cx<float>* __restric
 #pragma unroll
     for (int q = 0; q < C; q += 2) g4[q >> 1] = make_float4(acc[q].x, acc[q].y, acc[q + 1].x, acc[q + 1].y);
   }
+}
+
+template <int TILE, int C>
+__global__ __launch_bounds__(1024) void k_merge_pairs(const cx<float>* __restrict__ partials,
+                                                      const int32_t* __restrict__ bin_tasks,
+                                                      const int32_t* __restrict__ order,
+                                                      cx<float>* __restrict__ grid, int nb, int K,
+                                                      int R, double r2,
+                                                      int32_t* __restrict__ mlist) {
+  merge_pairs_body<TILE, C>(blockIdx.x, partials, bin_tasks, order, grid, nb, K, R, r2, mlist);
 }
 
 // ---------------------------------------------------------------------------
