@@ -419,6 +419,18 @@ int nufftct_batch_create(nufftct_batch** out, int nvol, const int64_t* N, const 
                          const double* const* dirs, const int64_t* n_lines,
                          const int64_t* n_r, void* stream);
 
+/*
+ * As nufftct_batch_create, with each size class (volumes of equal N, K and
+ * n_r) taking the tiling that nufftct_autotune_radial picks on the class
+ * member with the most lines (which also records it for plans of that
+ * geometry).  Tuning runs candidate plans on the GPU: seconds for large
+ * classes.  Errors as nufftct_batch_create, plus EHIP from the tuner.
+ */
+int nufftct_batch_create_tuned(nufftct_batch** out, int nvol, const int64_t* N, const int64_t* K,
+                               int J, int kernel, double beta, int precision,
+                               const double* const* dirs, const int64_t* n_lines,
+                               const int64_t* n_r, void* stream);
+
 /* vols[b], outs[b]: device pointers per volume (sizes as for that volume's plan);
  * flags as for nufftct_forward / nufftct_adjoint (DETERMINISTIC included). */
 int nufftct_batch_forward(nufftct_batch* batch, const void* const* vols, void* const* outs,

@@ -400,9 +400,11 @@ class Grangeat:
 
 
 class Batch:
-    """Uneven batch of radial plans sharing J, kernel and precision."""
+    """Uneven batch of radial plans sharing J, kernel and precision; tune=True
+    autotunes the tiling per size class (on its largest member)."""
 
-    def __init__(self, Ns, Ks, J, dirs_list, n_rs, *, kernel="kb", beta=None, dtype=None):
+    def __init__(self, Ns, Ks, J, dirs_list, n_rs, *, kernel="kb", beta=None, dtype=None,
+                 tune=False):
         torch = _torch()
         lib = _lib.load()
         self.dtype = dtype or torch.complex64
@@ -419,9 +421,10 @@ class Batch:
         Ra = (C.c_int64 * n)(*self.n_rs)
         Da = (C.POINTER(C.c_double) * n)(*[d.ctypes.data_as(C.POINTER(C.c_double)) for d in self._dirs])
         self._ptr = C.c_void_p()
-        _lib.check(lib.nufftct_batch_create(C.byref(self._ptr), n, Na, Ka, int(J), kern,
-                                            -1.0 if beta is None else float(beta), prec, Da, La,
-                                            Ra, C.c_void_p(_stream_handle())))
+        create = lib.nufftct_batch_create_tuned if tune else lib.nufftct_batch_create
+        _lib.check(create(C.byref(self._ptr), n, Na, Ka, int(J), kern,
+                          -1.0 if beta is None else float(beta), prec, Da, La, Ra,
+                          C.c_void_p(_stream_handle())))
 
     def close(self):
         if getattr(self, "_ptr", None) is not None and self._ptr.value:

@@ -64,6 +64,9 @@ SIGNATURES = {
     "nufftct_batch_create": (C.c_int, [C.POINTER(_p), C.c_int, C.POINTER(_i64), C.POINTER(_i64),
                                        C.c_int, C.c_int, C.c_double, C.c_int, C.POINTER(_dp),
                                        C.POINTER(_i64), C.POINTER(_i64), _p]),
+    "nufftct_batch_create_tuned": (C.c_int, [C.POINTER(_p), C.c_int, C.POINTER(_i64), C.POINTER(_i64),
+                                       C.c_int, C.c_int, C.c_double, C.c_int, C.POINTER(_dp),
+                                       C.POINTER(_i64), C.POINTER(_i64), _p]),
     "nufftct_batch_forward": (C.c_int, [_p, C.POINTER(_p), C.POINTER(_p), C.c_int, _p]),
     "nufftct_batch_adjoint": (C.c_int, [_p, C.POINTER(_p), C.POINTER(_p), C.c_int, _p]),
     "nufftct_batch_graph_capture": (C.c_int, [_p, C.c_int, C.POINTER(_p), C.POINTER(_p),

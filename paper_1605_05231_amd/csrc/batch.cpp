@@ -356,21 +356,45 @@ static int run_dir(nufftct_batch* b, int dir, const void* const* src, void* cons
   return rc;
 }
 
-extern "C" {
-
-int nufftct_batch_create(nufftct_batch** out, int nvol, const int64_t* N, const int64_t* K, int J,
-                         int kernel, double beta, int precision, const double* const* dirs,
-                         const int64_t* n_lines, const int64_t* n_r, void* stream) {
+// Batch creation; with `tune`, each size class (equal N, K, n_r) takes the
+// tiling the autotuner picks on its member with the most points.
+static int batch_create(nufftct_batch** out, int nvol, const int64_t* N, const int64_t* K, int J,
+                        int kernel, double beta, int precision, const double* const* dirs,
+                        const int64_t* n_lines, const int64_t* n_r, void* stream, bool tune) {
   if (!out) return bfail(NUFFTCT_EINVAL, "out is NULL");
   *out = nullptr;
   if (nvol < 1 || !N || !K || !dirs || !n_lines || !n_r)
     return bfail(NUFFTCT_EINVAL, "nvol must be >= 1 and the size arrays non-NULL");
   nufftct_batch* b = new (std::nothrow) nufftct_batch();
   if (!b) return bfail(NUFFTCT_ENOMEM, "host allocation failed");
+  std::vector<int> tile(nvol, 0), max_pts(nvol, 0);
+  if (tune) {
+    std::vector<bool> done(nvol, false);
+    for (int i = 0; i < nvol; ++i) {
+      if (done[i]) continue;
+      int big = i;  // the class member with the most points
+      for (int j = i; j < nvol; ++j)
+        if (N[j] == N[i] && K[j] == K[i] && n_r[j] == n_r[i] && n_lines[j] > n_lines[big]) big = j;
+      int t = 0, mp = 0;
+      if (nufftct_autotune_radial(N[big], K[big], J, kernel, beta, precision, dirs[big],
+                                  n_lines[big], n_r[big], NUFFTCT_DERIV_RADIAL, &t, &mp, nullptr,
+                                  stream)) {
+        std::string m = "autotuning volume " + std::to_string(big) + ": " + nufftct_last_error();
+        free_batch(b);
+        return bfail(NUFFTCT_EHIP, m);
+      }
+      for (int j = i; j < nvol; ++j)
+        if (N[j] == N[i] && K[j] == K[i] && n_r[j] == n_r[i]) {
+          tile[j] = t;
+          max_pts[j] = mp;
+          done[j] = true;
+        }
+    }
+  }
   for (int i = 0; i < nvol; ++i) {
     nufftct_plan* p = nullptr;
-    int rc = nufftct_plan_create_radial(&p, N[i], K[i], J, kernel, beta, precision, dirs[i],
-                                        n_lines[i], n_r[i], stream);
+    int rc = plan_create_radial_tiled(&p, N[i], K[i], J, kernel, beta, precision, dirs[i],
+                                      n_lines[i], n_r[i], tile[i], max_pts[i], stream);
     if (rc) {
       std::string m = "volume " + std::to_string(i) + ": " + nufftct_last_error();
       free_batch(b);
@@ -404,6 +428,23 @@ int nufftct_batch_create(nufftct_batch** out, int nvol, const int64_t* N, const 
   }
   *out = b;
   return NUFFTCT_OK;
+}
+
+extern "C" {
+
+int nufftct_batch_create(nufftct_batch** out, int nvol, const int64_t* N, const int64_t* K, int J,
+                         int kernel, double beta, int precision, const double* const* dirs,
+                         const int64_t* n_lines, const int64_t* n_r, void* stream) {
+  return batch_create(out, nvol, N, K, J, kernel, beta, precision, dirs, n_lines, n_r, stream,
+                      false);
+}
+
+int nufftct_batch_create_tuned(nufftct_batch** out, int nvol, const int64_t* N, const int64_t* K,
+                               int J, int kernel, double beta, int precision,
+                               const double* const* dirs, const int64_t* n_lines,
+                               const int64_t* n_r, void* stream) {
+  return batch_create(out, nvol, N, K, J, kernel, beta, precision, dirs, n_lines, n_r, stream,
+                      true);
 }
 
 int nufftct_batch_forward(nufftct_batch* b, const void* const* vols, void* const* outs, int flags,

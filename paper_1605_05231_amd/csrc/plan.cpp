@@ -671,6 +671,21 @@ int nufftct_plan_create_radial(nufftct_plan** out, int64_t N, int64_t K, int J, 
                 (hipStream_t)stream, 0, 0);
 }
 
+}  // extern "C"
+
+int plan_create_radial_tiled(nufftct_plan** out, int64_t N, int64_t K, int J, int kernel,
+                             double beta, int precision, const double* dirs, int64_t n_lines,
+                             int64_t n_r, int tile, int max_pts, void* stream) {
+  if (n_lines < 1 || n_r < 4 || n_lines > ((int64_t)1 << 31) / n_r) {
+    if (out) *out = nullptr;
+    return fail(NUFFTCT_EINVAL, "bad radial geometry");
+  }
+  return create(out, N, K, J, kernel, beta, precision, n_lines * n_r, n_r, true, dirs, n_lines,
+                (hipStream_t)stream, tile, max_pts);
+}
+
+extern "C" {
+
 int nufftct_autotune_radial(int64_t N, int64_t K, int J, int kernel, double beta, int precision,
                             const double* dirs, int64_t n_lines, int64_t n_r, int flags,
                             int* best_tile, int* best_max_pts, double* best_ms, void* stream) {

@@ -131,5 +131,10 @@ template <typename T>
 hipError_t launch_merge(const nufftct_plan& p, void* grid, hipStream_t s, bool prune);
 
 bool fft_length_supported(int64_t L);
+// a radial plan with its tiling given (tile edge, points per task; 0 = the
+// usual choice)
+int plan_create_radial_tiled(nufftct_plan** out, int64_t N, int64_t K, int J, int kernel,
+                             double beta, int precision, const double* dirs, int64_t n_lines,
+                             int64_t n_r, int tile, int max_pts, void* stream);
 // record this thread's error message (read back by nufftct_last_error); returns code
 int set_last_error(int code, const std::string& msg);

@@ -98,6 +98,35 @@ def test_many_small_volumes_in_chunks():
         assert max(e, ea) < 1e-5
 
 
+def test_tuned_batch_vs_oracle():
+    """A batch whose size classes take the autotuner's tiling: every member
+    matches the oracle, and the members of a class share one tiling."""
+    require_gpu()
+    import torch
+    import paper_1605_05231_amd as pkg
+    spec = [(48, 12), (48, 10), (64, 8), (32, 16), (64, 10)]
+    items = [synthetic.Workload(f"u{i}", N=n, K=2 * n, J=6, n_phi=p, n_theta=p // 2, n_r=2 * n,
+                                n_ell=10, seed=5400 + i) for i, (n, p) in enumerate(spec)]
+    dirs = [w.directions() for w in items]
+    b = pkg.Batch([w.N for w in items], [w.K for w in items], 6, dirs, [w.n_r for w in items],
+                  tune=True)
+    xs = [torch.from_numpy(w.volume().astype(np.complex64)).cuda() for w in items]
+    outs = [torch.empty(w.M, dtype=torch.complex64, device="cuda") for w in items]
+    vols = [torch.empty(w.N ** 3, dtype=torch.complex64, device="cuda") for w in items]
+    b.forward(xs, outs)
+    b.adjoint(outs, vols)
+    torch.cuda.synchronize()
+    for i, w in enumerate(items):
+        prm = nufft.Params(w.N, w.K, 6)
+        x = xs[i].cpu().numpy().astype(complex)
+        want = projector.forward(x, dirs[i], w.n_r, prm)
+        got = outs[i].cpu().numpy()
+        wa = projector.adjoint(got.astype(complex), dirs[i], w.n_r, prm)
+        ef, ea = rel_l2(got, want), rel_l2(vols[i].cpu().numpy(), wa.reshape(-1))
+        say(f"tuned batch item {i} N={w.N}: fwd {ef:.2e} adj {ea:.2e}")
+        assert max(ef, ea, max_rel(got, want)) < 1e-5
+
+
 def test_minmax_batch_matches_single_plans():
     """Min-max weights differ per volume, so such a batch runs volume by volume
     on worker streams: its results equal single plans' bit for bit."""
