@@ -123,15 +123,19 @@ __global__ __launch_bounds__(kgrid::GridCfg<T>::NT_SPREAD) void k_spread_rest_b(
   }
 }
 
-template <int TILE, int C>
-__global__ __launch_bounds__(1024) void k_merge_pairs_b(const BatchPointVol* __restrict__ vols,
-                                                        BatchStarts start, int nv) {
-  const int v = find_vol(start, nv, blockIdx.x);
-  const BatchPointVol& d = vols[v];
-  kgrid::merge_pairs_body<TILE, C>(blockIdx.x - start.s[v], (const cx<float>*)d.partials,
-                                   d.bin_tasks, d.merge_order, (cx<float>*)d.grid, d.nb, d.K,
-                                   d.R, d.r2, d.multi);
-}
+// a batch's merge arguments: those of the volume of block b
+struct MergeBatchArgs {
+  const BatchPointVol* vols;
+  BatchStarts start;
+  int nv;
+  __device__ __forceinline__ kgrid::MergeArgs resolve(unsigned b, unsigned& bx) const {
+    const int v = find_vol(start, nv, b);
+    const BatchPointVol& d = vols[v];
+    bx = b - (unsigned)start.s[v];
+    return kgrid::MergeArgs{(const cx<float>*)d.partials, d.bin_tasks, d.merge_order,
+                            (cx<float>*)d.grid, d.nb, d.K, d.R, d.r2, d.multi};
+  }
+};
 
 template <typename T, int TILE>
 __global__ __launch_bounds__(TILE * TILE * TILE < 1024 ? TILE * TILE * TILE : 1024) void k_merge_b(
@@ -240,8 +244,9 @@ hipError_t point_stage(const BatchGroup& g, int what, bool det, const WeightPoly
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (F32 && TILE == 16)
-      hipLaunchKernelGGL((k_merge_pairs_b<16, 2>), dim3((unsigned)g.start_tiles.s[g.nv]), dim3(1024), 0, st,
-                         g.vols, g.start_tiles, g.nv);
+      hipLaunchKernelGGL((kgrid::k_merge_pairs<16, 2, MergeBatchArgs>),
+                         dim3((unsigned)g.start_tiles.s[g.nv]), dim3(1024), 0, st,
+                         MergeBatchArgs{g.vols, g.start_tiles, g.nv});
     else
       hipLaunchKernelGGL((k_merge_b<T, TILE>), dim3((unsigned)g.start_tiles.s[g.nv]),
                          dim3(TILE * TILE * TILE < 1024 ? TILE * TILE * TILE : 1024), 0, st, g.vols,

@@ -1125,12 +1125,35 @@ __global__ __launch_bounds__(TILE * TILE * TILE < 1024 ? TILE * TILE * TILE : 10
 // in 16-byte pairs (part_base offsets and the per-task stride are even), the
 // short-row blocks one value at a time; the per-cell summation order is the
 // one of k_merge.
-template <int TILE, int C>
-__device__ __forceinline__ void merge_pairs_body(int bx, const cx<float>* __restrict__ partials,
-                                                 const int32_t* __restrict__ bin_tasks,
-                                                 const int32_t* __restrict__ order,
-                                                 cx<float>* __restrict__ grid, int nb, int K,
-                                                 int R, double r2, int32_t* __restrict__ mlist) {
+// Its arguments: one plan's (MergeArgs) or, in a batch, those of the
+// volume a block belongs to (the argument type resolves them from the block
+// index); the body is the kernel's own, so that the one-plan kernel compiles
+// as a plain kernel.
+struct MergeArgs {
+  const cx<float>* partials;
+  const int32_t* bin_tasks;
+  const int32_t* order;
+  cx<float>* grid;
+  int nb, K, R;
+  double r2;
+  int32_t* mlist;
+  __device__ __forceinline__ MergeArgs resolve(unsigned b, unsigned& bx) const {
+    bx = b;
+    return *this;
+  }
+};
+
+template <int TILE, int C, typename A>
+__global__ __launch_bounds__(1024) void k_merge_pairs(A args) {
+  unsigned bx;
+  const MergeArgs a = args.resolve(blockIdx.x, bx);
+  const cx<float>* __restrict__ partials = a.partials;
+  const int32_t* __restrict__ bin_tasks = a.bin_tasks;
+  const int32_t* __restrict__ order = a.order;
+  cx<float>* __restrict__ grid = a.grid;
+  const int nb = a.nb, K = a.K, R = a.R;
+  const double r2 = a.r2;
+  int32_t* __restrict__ mlist = a.mlist;
   // the spreading's list of multi-class tasks has been consumed: empty it
   if (mlist && bx == 0 && threadIdx.x == 0) mlist[0] = 0;
   constexpr int TTC = TILE * TILE * TILE / C;
@@ -1221,15 +1244,6 @@ __device__ __forceinline__ void merge_pairs_body(int bx, const cx<float>* __rest
   }
 }
 
-template <int TILE, int C>
-__global__ __launch_bounds__(1024) void k_merge_pairs(const cx<float>* __restrict__ partials,
-                                                      const int32_t* __restrict__ bin_tasks,
-                                                      const int32_t* __restrict__ order,
-                                                      cx<float>* __restrict__ grid, int nb, int K,
-                                                      int R, double r2,
-                                                      int32_t* __restrict__ mlist) {
-  merge_pairs_body<TILE, C>(blockIdx.x, partials, bin_tasks, order, grid, nb, K, R, r2, mlist);
-}
 
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -1326,10 +1340,9 @@ hipError_t merge(const nufftct_plan& p, void* grid, hipStream_t st, bool prune) 
   const double r2 = prune ? p.ball_r2 : 1e300;
   const dim3 grd((unsigned)((int64_t)p.nb * p.nb * p.nb));
   if (p.tile == 16 && sizeof(T) == 4) {
-    hipLaunchKernelGGL((k_merge_pairs<16, 2>), grd, dim3(1024), 0, st,
-                       (const cx<float>*)p.d_partials,
-                       p.d_bin_tasks, p.d_merge_order, (cx<float>*)grid, p.nb, (int)p.K, R, r2,
-                       p.d_multi);
+    const MergeArgs a{(const cx<float>*)p.d_partials, p.d_bin_tasks, p.d_merge_order,
+                      (cx<float>*)grid, p.nb, (int)p.K, R, r2, p.d_multi};
+    hipLaunchKernelGGL((k_merge_pairs<16, 2, MergeArgs>), grd, dim3(1024), 0, st, a);
     return hipGetLastError();
   }
   if (p.tile == 16)
