@@ -53,14 +53,20 @@ void point_omega(const BinParams& p, const std::vector<double>& geom, int64_t i,
 //     spreads both, summing their contributions to each of the J^3 cells
 //     before one LDS atomic); the pairs come first, then the unpaired
 //     points (FP32 with Kaiser-Bessel weights; the other kernels spread one
-//     point at a time, and their tasks hold no pairs).  Cell c = (l0 S + l1) S + l2 (S = tile + J - 1); pairs, then
-//     singles, dealt round-robin over the residues c mod 32, so the lanes of
-//     a wave start on distinct banks and a tap offset shared by all lanes
-//     keeps them so;
+//     point at a time, and their tasks hold no pairs).  Cell
+//     c = (l0 S + l1) S + l2 (S = tile + J - 1); pairs, then singles, dealt
+//     round-robin over the residues c mod 32, so the lanes of a wave start
+//     on distinct banks and a tap offset shared by all lanes keeps them so;
 //   interpolation (FP32): rows padded to even pitch S2, cell
 //     c = (l0 S + l1) S2 + l2; even cells first, then odd ones (a wave's
 //     row reads then share one alignment), each class dealt round-robin over
 //     its 16 residues mod 32.  FP64 interpolation uses the spreading order.
+// With `twins` (FP32), each bin is first put in the order of its points'
+// cells and frequencies, so that the two points of a frequency sampled twice
+// (as lines in opposite directions sample it) become one pair; the pairs
+// whose frequencies agree to 1e-12 (relative) then come first in both
+// orders: one evaluation of the weights serves both points in spreading, and
+// one interpolation both outputs.
 void build_bins(const BinParams& p, const std::vector<double>& geom, Binning& B) {
   const int64_t M = p.M;
   const int nb = p.nb, T = p.tile, J = p.J;
@@ -102,6 +108,38 @@ void build_bins(const BinParams& p, const std::vector<double>& geom, Binning& B)
     std::vector<int64_t> pos(off.begin(), off.end() - 1);
     for (int64_t i = 0; i < M; ++i) B.perm_s[pos[key[i]]++] = (int32_t)i;
   }
+  if (p.twins) {
+    // each bin in the order of its points' first tap cells, then of their
+    // frequencies quantised to 2^-30: the two points of a frequency sampled
+    // twice become neighbours, in one task and one pair
+    struct QKey {
+      uint16_t cell;
+      int64_t q[3];
+      int32_t pt;
+    };
+    parallel(nbins, [&](int64_t a, int64_t b) {
+      std::vector<QKey> qk;
+      for (int64_t bin = a; bin < b; ++bin) {
+        const int64_t s = off[bin], n = off[bin + 1] - s;
+        qk.resize(n);
+        for (int64_t i = 0; i < n; ++i) {
+          double om[3];
+          const int32_t pt = B.perm_s[s + i];
+          point_omega(p, geom, pt, om);
+          qk[i].cell = lcell[pt];
+          for (int c = 0; c < 3; ++c) qk[i].q[c] = std::llround(std::ldexp(om[c], 30));
+          qk[i].pt = pt;
+        }
+        std::stable_sort(qk.begin(), qk.end(), [](const QKey& x, const QKey& y) {
+          if (x.cell != y.cell) return x.cell < y.cell;
+          for (int c = 0; c < 3; ++c)
+            if (x.q[c] != y.q[c]) return x.q[c] < y.q[c];
+          return false;
+        });
+        for (int64_t i = 0; i < n; ++i) B.perm_s[s + i] = qk[i].pt;
+      }
+    });
+  }
   B.tasks.clear();
   B.bin_tasks.assign(nbins + 1, 0);
   for (int64_t b = 0; b < nbins; ++b) {
@@ -113,6 +151,7 @@ void build_bins(const BinParams& p, const std::vector<double>& geom, Binning& B)
       t.start = (int32_t)q;
       t.count = (int32_t)std::min<int64_t>(p.max_pts, e - q);
       t.npairs = 0;
+      t.ntwins = 0;
       B.tasks.push_back(t);
     }
   }
@@ -175,7 +214,7 @@ void build_bins(const BinParams& p, const std::vector<double>& geom, Binning& B)
   };
   parallel((int64_t)B.tasks.size(), [&](int64_t a, int64_t b) {
     Deal d;
-    std::vector<int32_t> sorted, first_of, singles, idx;
+    std::vector<int32_t> sorted, first_of, singles, idx, twin_first, other_first, rest;
     std::vector<uint8_t> res_pair;
     for (int64_t k = a; k < b; ++k) {
       TileTask& t = B.tasks[k];
@@ -186,35 +225,81 @@ void build_bins(const BinParams& p, const std::vector<double>& geom, Binning& B)
         d.run(B.perm.data() + t.start, t.count, pairs ? res_i.data() : res_s.data(), pairs ? 2 : 1);
         continue;
       }
-      // pair the points of each first tap cell (in point order within it)
+      // pair the points of each first tap cell (in the bin's order within it)
       sorted.assign(ps, ps + t.count);
       std::stable_sort(sorted.begin(), sorted.end(),
                        [&](int32_t x, int32_t y) { return lcell[x] < lcell[y]; });
       first_of.clear();
       singles.clear();
-      res_pair.clear();
       for (int i = 0; i < t.count;) {
         int j = i;
         while (j < t.count && lcell[sorted[j]] == lcell[sorted[i]]) ++j;
         for (int q = i; q + 1 < j; q += 2) {
           first_of.push_back(q);  // pair (sorted[q], sorted[q + 1])
-          res_pair.push_back(res_s[sorted[q]]);
         }
         if ((j - i) & 1) singles.push_back(sorted[j - 1]);
         i = j;
       }
-      const int np = (int)first_of.size();
-      idx.resize(np);
-      for (int q = 0; q < np; ++q) idx[q] = q;
-      d.run(idx.data(), np, res_pair.data(), 1);
-      for (int q = 0; q < np; ++q) {
-        ps[2 * q] = sorted[first_of[idx[q]]];
-        ps[2 * q + 1] = sorted[first_of[idx[q]] + 1];
+      // with `twins`, the pairs whose two frequencies agree to 1e-12
+      // (relative) come first, in both orders
+      auto is_twin = [&](int32_t x, int32_t y) {
+        double oa[3], ob[3];
+        point_omega(p, geom, x, oa);
+        point_omega(p, geom, y, ob);
+        double dmax = 0.0, amax = 1.0;
+        for (int c = 0; c < 3; ++c) {
+          dmax = std::max(dmax, std::fabs(oa[c] - ob[c]));
+          amax = std::max(amax, std::fabs(oa[c]));
+        }
+        return dmax <= 1e-12 * amax;
+      };
+      twin_first.clear();
+      other_first.clear();
+      for (int32_t q : first_of)
+        (p.twins && is_twin(sorted[q], sorted[q + 1]) ? twin_first : other_first).push_back(q);
+      const int nt = (int)twin_first.size(), np = (int)first_of.size();
+      // spreading order: twin pairs, other pairs, single points, each dealt
+      // over the residues of their first cells
+      int32_t* o = ps;
+      for (const std::vector<int32_t>* set : {&twin_first, &other_first}) {
+        const int n = (int)set->size();
+        idx.resize(n);
+        res_pair.resize(n);
+        for (int q = 0; q < n; ++q) {
+          idx[q] = q;
+          res_pair[q] = res_s[sorted[(*set)[q]]];
+        }
+        d.run(idx.data(), n, res_pair.data(), 1);
+        for (int q = 0; q < n; ++q) {
+          *o++ = sorted[(*set)[idx[q]]];
+          *o++ = sorted[(*set)[idx[q]] + 1];
+        }
       }
       d.run(singles.data(), (int)singles.size(), res_s.data(), 1);
-      std::copy(singles.begin(), singles.end(), ps + 2 * np);
+      std::copy(singles.begin(), singles.end(), o);
       t.npairs = np;
-      d.run(B.perm.data() + t.start, t.count, pairs ? res_i.data() : res_s.data(), pairs ? 2 : 1);
+      t.ntwins = nt;
+      if (!p.twins) {
+        d.run(B.perm.data() + t.start, t.count, pairs ? res_i.data() : res_s.data(), pairs ? 2 : 1);
+        continue;
+      }
+      // interpolation order: the twin pairs (one unit each), then every
+      // other point, each dealt over its residues
+      int32_t* pi = B.perm.data() + t.start;
+      idx.resize(nt);
+      res_pair.resize(nt);
+      for (int q = 0; q < nt; ++q) {
+        idx[q] = q;
+        res_pair[q] = res_i[ps[2 * q]];
+      }
+      d.run(idx.data(), nt, res_pair.data(), 2);
+      for (int q = 0; q < nt; ++q) {
+        pi[2 * q] = ps[2 * idx[q]];
+        pi[2 * q + 1] = ps[2 * idx[q] + 1];
+      }
+      rest.assign(ps + 2 * nt, ps + t.count);
+      d.run(rest.data(), (int)rest.size(), res_i.data(), 2);
+      std::copy(rest.begin(), rest.end(), pi + 2 * nt);
     }
   });
 }

@@ -13,6 +13,9 @@ struct TileTask {
   int32_t count;   // number of points
   int32_t npairs;  // spreading order: its first 2 npairs entries are npairs
                    // pairs of points that share their first tap cell
+  int32_t ntwins;  // both orders: their first 2 ntwins entries are ntwins
+                   // pairs of points at the same frequency (to FP64
+                   // rounding), whose weights serve both points
 };
 
 namespace hostplan {
@@ -23,6 +26,7 @@ struct BinParams {
   bool radial = false;
   bool fp32 = true;         // interpolation order for FP32 pair reads
   bool pair_spread = true;  // spreading pairs points that share a first tap cell
+  bool twins = false;       // interpolation pairs points at the same frequency
 };
 
 struct Binning {

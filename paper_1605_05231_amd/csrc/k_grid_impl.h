@@ -344,24 +344,30 @@ __device__ __forceinline__ void interp_body(int64_t bx, const cx<T>* __restrict_
     }
   }
   __syncthreads();
-  // the next point one iteration ahead: its whole geometry (FP64), or only its
+  // Units of the task's interpolation order: unit u < ntwins is the pair of
+  // points at entries 2u, 2u + 1 (one frequency sampled twice: one
+  // evaluation, two outputs), unit u >= ntwins the point at entry ntwins + u.
+  const int nt = tk.ntwins, nunits = tk.count - nt;
+  auto entry = [&](int u) { return tk.start + (u < nt ? 2 * u : nt + u); };
+  // the next unit one iteration ahead: its whole geometry (FP64), or only its
   // id (FP32, whose register budget has no room for the geometry)
   PtRaw nxt;
   int pnxt = 0;
-  if ((int)threadIdx.x < tk.count) {
-    if constexpr (GridCfg<T>::PREFETCH_GEOM) nxt = fetch_point(g, perm, tk.start + threadIdx.x);
-    else pnxt = perm[tk.start + threadIdx.x];
+  if ((int)threadIdx.x < nunits) {
+    if constexpr (GridCfg<T>::PREFETCH_GEOM) nxt = fetch_point(g, perm, entry(threadIdx.x));
+    else pnxt = perm[entry(threadIdx.x)];
   }
-  for (int i = threadIdx.x; i < tk.count; i += NT_INTERP) {
+  for (int i = threadIdx.x; i < nunits; i += NT_INTERP) {
     PtRaw cur;
     if constexpr (GridCfg<T>::PREFETCH_GEOM) {
       cur = nxt;
-      if (i + NT_INTERP < tk.count) nxt = fetch_point(g, perm, tk.start + i + NT_INTERP);
+      if (i + NT_INTERP < nunits) nxt = fetch_point(g, perm, entry(i + NT_INTERP));
     } else {
       cur = point_of(g, pnxt);
-      if (i + NT_INTERP < tk.count) pnxt = perm[tk.start + i + NT_INTERP];
+      if (i + NT_INTERP < nunits) pnxt = perm[entry(i + NT_INTERP)];
     }
     const int p = cur.p;
+    const int p2 = i < nt ? perm[tk.start + 2 * i + 1] : -1;  // the unit's second point
     int first[3];
     double frac[3];
     point_taps<sizeof(T) == 4>(g, cur, J, first, frac);
@@ -392,6 +398,7 @@ __device__ __forceinline__ void interp_body(int64_t bx, const cx<T>* __restrict_
       acc = gather<T, J, S, S2, CW, 0>(tile, grid, K, first, l0, l1, l2, inside, w0r, w0i, w1r,
                                        w1i, w2r, w2i);
     out[p] = acc;
+    if (p2 >= 0) out[p2] = acc;
   }
 }
 
@@ -719,9 +726,11 @@ __device__ __forceinline__ void spread_task(int64_t task_id, const cx<T>* __rest
   // 2u + 1, u < npairs), then single points (entry npairs + u)
   // FP32 with real weights: both points' contributions to a cell summed
   // before one atomic; otherwise (min-max weights, or FP64, whose register
-  // budget it would exceed) the points of a unit are spread one by one
+  // budget it would exceed) the points of a unit are spread one by one.
+  // The first ntwins pairs sample one frequency twice: their weights are
+  // evaluated once and spread the sum of the two values.
   constexpr bool PAIRED = !CW && sizeof(T) == 4;
-  const int np = tk.npairs, nunits = tk.count - np;
+  const int np = tk.npairs, nunits = tk.count - np, nt = tk.ntwins;
   cx<T>* dst = partials + task_id * (int64_t)part_stride(TILE, R);
   // no accumulation is needed when every value is zero or non-finite
   const bool work = !FIXED || vmax > (T)0;
@@ -769,7 +778,10 @@ __device__ __forceinline__ void spread_task(int64_t task_id, const cx<T>* __rest
       nxt = fetch_point(g, perm, tk.start + e);
       vnxt = in[nxt.p];
       vnxt2 = cx<T>{0, 0};
-      if (PAIRED && u < np) {
+      if (PAIRED && u < nt) {
+        nxt2.p = perm[tk.start + e + 1];  // (a twin's geometry is the first point's)
+        vnxt2 = in[nxt2.p];
+      } else if (PAIRED && u < np) {
         nxt2 = fetch_point(g, perm, tk.start + e + 1);
         vnxt2 = in[nxt2.p];
       }
@@ -805,6 +817,7 @@ __device__ __forceinline__ void spread_task(int64_t task_id, const cx<T>* __rest
         const bool nz = v.x != (T)0 || v.y != (T)0 || (pair && (v2.x != (T)0 || v2.y != (T)0));
         if (!nz && !bad1 && !bad2) continue;
       }
+      const bool twin = PAIRED && u < nt;
       int first[3], first2[3] = {0, 0, 0};
       double frac[3], frac2[3] = {0.0, 0.0, 0.0};
       point_taps<sizeof(T) == 4>(g, cur, J, first, frac);
@@ -818,7 +831,12 @@ __device__ __forceinline__ void spread_task(int64_t task_id, const cx<T>* __rest
       axis_weights<T, J, DEG, CW>(P, frac[1], w1r, w1i);
       axis_weights<T, J, DEG, CW>(P, frac[2], w2r, w2i);
       bool same = true;  // the second point shares the first tap cell
-      if (pair) {
+      if (twin) {
+        // the host found both points in one cell with FP64 frequencies that
+        // agree to 1e-12, far below the FP32 weights' resolution
+#pragma unroll
+        for (int d = 0; d < 3; ++d) first2[d] = first[d];
+      } else if (pair) {
         point_taps<sizeof(T) == 4>(g, cur2, J, first2, frac2);
         same = first2[0] == first[0] && first2[1] == first[1] && first2[2] == first[2];
       }
@@ -834,7 +852,12 @@ __device__ __forceinline__ void spread_task(int64_t task_id, const cx<T>* __rest
         const T a1 = fmax(fabs(vs1.x), fabs(vs1.y)), a2 = fmax(fabs(vs2.x), fabs(vs2.y));
         tmn = fmin(tmn, fmin(a1 > (T)0 ? a1 : (T)INFINITY, a2 > (T)0 ? a2 : (T)INFINITY));
       }
-      if constexpr (PAIRED) {
+      if (twin) {
+        const cx<T> vs = {v.x + v2.x, v.y + v2.y};
+        if (in1)
+          spread_one<T, J, S, SS, false, FIXED>(accp, acc, vs, (l0 * S + l1) * S + l2, w0r, w0i,
+                                                w1r, w1i, w2r, w2i);
+      } else if constexpr (PAIRED) {
         // (a single point, or a pair whose first cells differ, adds a zero here)
         T x0r[J], x0i[J], x1r[J], x1i[J], x2r[J], x2i[J];
         const bool both = pair && same;
@@ -850,7 +873,7 @@ __device__ __forceinline__ void spread_task(int64_t task_id, const cx<T>* __rest
           spread_one<T, J, S, SS, CW, FIXED>(accp, acc, v, (l0 * S + l1) * S + l2, w0r, w0i, w1r,
                                              w1i, w2r, w2i);
       }
-      if (pair && (!PAIRED || !same)) {
+      if (pair && !twin && (!PAIRED || !same)) {
         // the second point on its own (or first cells that differ in the
         // device's rounding of a tie)
         const int m0 = first2[0] - o0, m1 = first2[1] - o1, m2 = first2[2] - o2;

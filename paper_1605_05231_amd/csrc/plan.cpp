@@ -360,6 +360,10 @@ static int create(nufftct_plan** out, int64_t N, int64_t K, int J, int kernel, d
     // the FP32 spreading with Kaiser-Bessel weights sums paired points'
     // contributions; the other kernels spread one point at a time
     bp.pair_spread = bp.fp32 && kernel != NUFFTCT_KERNEL_MINMAX_KB;
+    // the FP32 interpolation serves the two points of a frequency sampled
+    // twice with one evaluation (their frequencies agree to FP64 rounding,
+    // far below the FP32 result's precision)
+    bp.twins = bp.pair_spread;
     hostplan::build_bins(bp, g, B);
     p->ntasks = (int64_t)B.tasks.size();
     {

@@ -6,9 +6,9 @@
 //
 // usage: host_check <in> <out>
 //   in : int64 M, K, J, tile, max_pts, n_r, radial, fp32, pair_spread,
-//        n_geom, N, n_frac; double beta; double geom[3 n_geom]; double frac[n_frac]
+//        twins, n_geom, N, n_frac; double beta; double geom[3 n_geom]; double frac[n_frac]
 //   out: int32 first[3 M], int32 perm[M], int32 perm_s[M], int64 ntasks,
-//        int32 tasks[4 ntasks], int32 bin_tasks[nb^3 + 1], double s[N],
+//        int32 tasks[5 ntasks], int32 bin_tasks[nb^3 + 1], double s[N],
 //        double tw[2 K], double psi[J n_frac] (Kaiser-Bessel at the offsets
 //        u_j = J/2 - 1 - j + frac), double mm[2 J n_frac] (min-max
 //        coefficients, re/im interleaved)
@@ -43,8 +43,8 @@ int main(int argc, char** argv) {
   }
   FILE* fi = fopen(argv[1], "rb");
   if (!fi) return 2;
-  int64_t h[12];
-  rd(fi, h, 12);
+  int64_t h[13];
+  rd(fi, h, 13);
   double beta;
   rd(fi, &beta, 1);
   hostplan::BinParams bp;
@@ -57,8 +57,9 @@ int main(int argc, char** argv) {
   bp.radial = h[6] != 0;
   bp.fp32 = h[7] != 0;
   bp.pair_spread = h[8] != 0;
+  bp.twins = h[9] != 0;
   bp.nb = (int)(bp.K / bp.tile);
-  const int64_t n_geom = h[9], N = h[10], n_frac = h[11];
+  const int64_t n_geom = h[10], N = h[11], n_frac = h[12];
   std::vector<double> geom(3 * n_geom), frac(n_frac);
   rd(fi, geom.data(), geom.size());
   rd(fi, frac.data(), frac.size());
@@ -98,7 +99,7 @@ int main(int argc, char** argv) {
   wr(fo, B.perm.data(), B.perm.size());
   wr(fo, B.perm_s.data(), B.perm_s.size());
   wr(fo, &ntasks, 1);
-  wr(fo, reinterpret_cast<const int32_t*>(B.tasks.data()), 4 * B.tasks.size());
+  wr(fo, reinterpret_cast<const int32_t*>(B.tasks.data()), 5 * B.tasks.size());
   wr(fo, B.bin_tasks.data(), B.bin_tasks.size());
   wr(fo, s.data(), s.size());
   wr(fo, tw.data(), tw.size());

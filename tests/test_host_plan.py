@@ -52,13 +52,14 @@ def harness():
 
 
 def run(exe, *, K, J, N, geom, n_r=0, radial_plan=False, tile=16, max_pts=4096, fp32=True,
-        pair_spread=True, beta=None, fracs=(0.0, 0.25, 0.5, 0.999)):
+        pair_spread=True, twins=None, beta=None, fracs=(0.0, 0.25, 0.5, 0.999)):
+    twins = pair_spread if twins is None else twins
     beta = kernels.default_beta(J) if beta is None else beta
     geom = np.ascontiguousarray(np.asarray(geom, dtype=np.float64).reshape(-1, 3))
     M = geom.shape[0] * n_r if radial_plan else geom.shape[0]
     fr = np.asarray(fracs, dtype=np.float64)
     hdr = np.array([M, K, J, tile, max_pts, n_r, int(radial_plan), int(fp32), int(pair_spread),
-                    geom.shape[0], N, len(fr)], dtype=np.int64)
+                    int(twins), geom.shape[0], N, len(fr)], dtype=np.int64)
     with tempfile.TemporaryDirectory() as d:
         fi, fo = os.path.join(d, "in"), os.path.join(d, "out")
         with open(fi, "wb") as f:
@@ -80,7 +81,7 @@ def run(exe, *, K, J, N, geom, n_r=0, radial_plan=False, tile=16, max_pts=4096, 
     out = {"first": take(np.int32, 3 * M).reshape(M, 3), "perm": take(np.int32, M),
            "perm_s": take(np.int32, M)}
     nt = int(take(np.int64, 1)[0])
-    out["tasks"] = take(np.int32, 4 * nt).reshape(nt, 4)
+    out["tasks"] = take(np.int32, 5 * nt).reshape(nt, 5)
     out["bin_tasks"] = take(np.int32, nb ** 3 + 1)
     out["s"] = take(np.float64, N)
     out["tw"] = take(np.float64, 2 * K)
@@ -88,7 +89,8 @@ def run(exe, *, K, J, N, geom, n_r=0, radial_plan=False, tile=16, max_pts=4096, 
     mm = take(np.float64, 2 * J * len(fr)).reshape(len(fr), J, 2)
     out["mm"] = mm[..., 0] + 1j * mm[..., 1]
     assert o == len(buf)
-    out.update(M=M, nb=nb, tile=tile, max_pts=max_pts, J=J, K=K, N=N, fracs=fr, beta=beta)
+    out.update(M=M, nb=nb, tile=tile, max_pts=max_pts, J=J, K=K, N=N, fracs=fr, beta=beta,
+               twins=twins)
     return out
 
 
@@ -109,7 +111,8 @@ def check_binning(o, om, pair_spread):
     tasks, bt = o["tasks"], o["bin_tasks"]
     assert bt[0] == 0 and bt[-1] == len(tasks) and np.all(np.diff(bt) >= 0)
     pos = 0
-    for k, (b, start, count, npairs) in enumerate(tasks):
+    n_twins = n_same = 0
+    for k, (b, start, count, npairs, ntwins) in enumerate(tasks):
         assert bt[b] <= k < bt[b + 1]
         assert start == pos and 0 < count <= o["max_pts"]
         pos += count
@@ -120,7 +123,23 @@ def check_binning(o, om, pair_spread):
         assert 2 * npairs <= count and (pair_spread or npairs == 0)
         p = seg_s[:2 * npairs].reshape(-1, 2)
         assert np.array_equal(first[p[:, 0]], first[p[:, 1]])
+        # interpolation units: the first ntwins entry pairs sample one
+        # frequency twice, and they are exactly the spreading pairs that do
+        same = np.max(np.abs(om[p[:, 0]] - om[p[:, 1]]), axis=1) <= 1e-12 * np.maximum(
+            1.0, np.max(np.abs(om[p[:, 0]]), axis=1))
+        n_same += int(same.sum())
+        assert 2 * ntwins <= count and (o["twins"] or ntwins == 0)
+        assert np.all(same[:ntwins])  # twins first
+        tw = seg_i[:2 * ntwins].reshape(-1, 2)
+        assert np.array_equal(first[tw[:, 0]], first[tw[:, 1]])
+        assert np.all(np.abs(om[tw[:, 0]] - om[tw[:, 1]]) <= 1e-12 * np.maximum(1.0, np.abs(om[tw[:, 0]])))
+        if o["twins"]:
+            assert ntwins == same.sum() and not np.any(same[ntwins:])
+            want = {frozenset(q) for q in p[same].tolist()}
+            assert {frozenset(q) for q in tw.tolist()} == want
+        n_twins += int(ntwins)
     assert pos == M
+    return n_twins, n_same
 
 
 TIE_CASES = [
@@ -143,7 +162,20 @@ def test_first_taps_and_binning_radial(harness, case):
         o = run(harness, K=K, J=J, N=N, geom=dirs, n_r=n_r, radial_plan=True, tile=tile,
                 max_pts=max_pts)
         assert np.array_equal(o["first"], oracle_first(om, K, J)), name
-        check_binning(o, om, True)
+        n_twins, _ = check_binning(o, om, True)
+        # lines (phi, theta) and (phi + pi, pi - theta) sample the same
+        # frequencies in opposite order; the twins that can share an
+        # interpolation are those whose first taps agree (a tie can split
+        # them): nearly all of these must be found (a task boundary can
+        # split a few)
+        first = oracle_first(om, K, J)
+        groups = {}
+        for i, (qq, ff) in enumerate(zip(np.round(np.ldexp(om, 30)).astype(np.int64), first)):
+            groups.setdefault((tuple(qq), tuple(ff)), []).append(i)
+        possible = sum(len(v) // 2 for v in groups.values())
+        assert 0.95 * possible <= n_twins <= possible, (n_twins, possible)
+        if nphi % 2 == 0 and name != "k192_j6_ties":
+            assert n_twins >= 0.45 * len(om)
 
 
 def test_first_taps_explicit_adversarial_points(harness):
