@@ -155,9 +155,9 @@ hipError_t fwd_fft(const BatchClass<T>& c, const BatchArgs& a, hipStream_t st) {
   hipLaunchKernelGGL((k_pad_fft_x_b<T, L>), dim3((unsigned)((nlines + NLx - 1) / NLx), 1, c.nv),
                      dim3(kfft::NT), 0, st, a, c.s, c.tw_K, c.N);
   hipLaunchKernelGGL((k_fft_strided_b<T, L, -1>), dim3(L / NLc, c.N, c.nv), dim3(kfft::NTS), 0, st,
-                     a, c.tw_K, c.N, (int64_t)L, (int64_t)L * L, 1, 1, 0, 1, 0);
+                     a, c.tw_K, c.N, (int64_t)L, grid_plane_of<T>(L), 1, 1, 0, 1, 0);
   hipLaunchKernelGGL((k_fft_strided_b<T, L, -1>), dim3(L / NLc, L, c.nv), dim3(kfft::NTS), 0, st,
-                     a, c.tw_K, c.N, (int64_t)L * L, (int64_t)L, 0, 1, 0, 1, 1);
+                     a, c.tw_K, c.N, grid_plane_of<T>(L), (int64_t)L, 0, 1, 0, 1, 1);
   return hipGetLastError();
 }
 
@@ -167,9 +167,9 @@ hipError_t adj_fft(const BatchClass<T>& c, const BatchArgs& a, hipStream_t st) {
   constexpr int NLc = kfft::nl_col<T, L>();
   const int64_t nlines = (int64_t)c.N * c.N;
   hipLaunchKernelGGL((k_fft_strided_b<T, L, +1>), dim3(L / NLc, L, c.nv), dim3(kfft::NTS), 0, st,
-                     a, c.tw_K, c.N, (int64_t)L * L, (int64_t)L, 0, 0, 1, 2, 1);
+                     a, c.tw_K, c.N, grid_plane_of<T>(L), (int64_t)L, 0, 0, 1, 2, 1);
   hipLaunchKernelGGL((k_fft_strided_b<T, L, +1>), dim3(L / NLc, c.N, c.nv), dim3(kfft::NTS), 0, st,
-                     a, c.tw_K, c.N, (int64_t)L, (int64_t)L * L, 1, 0, 1, 2, 0);
+                     a, c.tw_K, c.N, (int64_t)L, grid_plane_of<T>(L), 1, 0, 1, 2, 0);
   hipLaunchKernelGGL((k_ifft_crop_x_b<T, L>), dim3((unsigned)((nlines + NLx - 1) / NLx), 1, c.nv),
                      dim3(kfft::NT), 0, st, a, c.s, c.tw_K, c.N);
   return hipGetLastError();

@@ -1,7 +1,8 @@
 // Deapodize/zero-pad + oversampled 3D FFT, inverse 3D FFT + crop/deapodize,
 // and the radial derivative DFT stage, as LDS-tiled kernels for gfx950.
 //
-// Grid layout: K^3 complex, last axis fastest, stored CENTRED: cell j of an
+// Grid layout: K^3 complex, last axis fastest, planes of axis 0 grid_plane
+// cells apart (K^2, padded for large planes), stored CENTRED: cell j of an
 // axis holds frequency kappa = j - K/2.  The centring costs nothing: the
 // padded input is multiplied by (-1)^(m0+m1+m2), which shifts the spectrum of
 // an unnormalised FFT by K/2 (folded into the deapodization factor).
@@ -93,7 +94,7 @@ __device__ __forceinline__ void pad_fft_x_body(int64_t bx, const cx<T>* __restri
     if (gl < nlines) {
       const int n0 = (int)gl / N, n1 = (int)gl % N;
       const int q0 = wrap_of(n0 - h, K), q1 = wrap_of(n1 - h, K);
-      grid[((int64_t)q0 * K + q1) * K + e] = buf[fft::addr<true, L, NL>(line, e)];
+      grid[(int64_t)q0 * grid_plane_of<T>(K) + (int64_t)q1 * K + e] = buf[fft::addr<true, L, NL>(line, e)];
     }
   }
 }
@@ -230,7 +231,7 @@ __device__ __forceinline__ void ifft_crop_x_body(int64_t bx, const cx<T>* __rest
         if (gl < nlines) {
           const int n0 = (int)gl / N, n1 = (int)gl % N;
           const int q0 = wrap_of(n0 - h, K), q1 = wrap_of(n1 - h, K);
-          v = grid[((int64_t)q0 * K + q1) * K + e];
+          v = grid[(int64_t)q0 * grid_plane_of<T>(K) + (int64_t)q1 * K + e];
         }
         return v;
       },
@@ -350,9 +351,9 @@ hipError_t pad_fft(const nufftct_plan& p, const void* vol, void* grid, hipStream
     hipLaunchKernelGGL((k_pad_fft_x<T, LL>), dim3((unsigned)((nlines + NLx - 1) / NLx)),      \
                        dim3(NT), 0, st, (const cx<T>*)vol, g, p.d_s, tw, N);                  \
     hipLaunchKernelGGL((k_fft_strided<T, LL, -1>), dim3(LL / NLc, N), dim3(NTS), 0, st, g, tw, \
-                       N, (int64_t)LL, (int64_t)LL * LL, 1, 1, 0, r2, ball, 0);              \
+                       N, (int64_t)LL, grid_plane_of<T>(LL), 1, 1, 0, r2, ball, 0);          \
     hipLaunchKernelGGL((k_fft_strided<T, LL, -1>), dim3(LL / NLc, LL), dim3(NTS), 0, st, g,    \
-                       tw, N, (int64_t)LL * LL, (int64_t)LL, 0, 1, 0, r2, ball, 1);          \
+                       tw, N, grid_plane_of<T>(LL), (int64_t)LL, 0, 1, 0, r2, ball, 1);      \
     return hipGetLastError();                                                                 \
   }
     KFFT_SIZES(CASE)
@@ -376,9 +377,9 @@ hipError_t ifft_crop(const nufftct_plan& p, void* grid, void* vol, hipStream_t s
     constexpr int NLc = nl_col<T, LL>();                                                      \
     const int64_t nlines = (int64_t)N * N;                                                    \
     hipLaunchKernelGGL((k_fft_strided<T, LL, +1>), dim3(LL / NLc, LL), dim3(NTS), 0, st, g,    \
-                       tw, N, (int64_t)LL * LL, (int64_t)LL, 0, 0, 1, r2, ball, 1);          \
+                       tw, N, grid_plane_of<T>(LL), (int64_t)LL, 0, 0, 1, r2, ball, 1);      \
     hipLaunchKernelGGL((k_fft_strided<T, LL, +1>), dim3(LL / NLc, N), dim3(NTS), 0, st, g, tw, \
-                       N, (int64_t)LL, (int64_t)LL * LL, 1, 0, 1, r2, ball, 0);              \
+                       N, (int64_t)LL, grid_plane_of<T>(LL), 1, 0, 1, r2, ball, 0);          \
     hipLaunchKernelGGL((k_ifft_crop_x<T, LL>), dim3((unsigned)((nlines + NLx - 1) / NLx)),    \
                        dim3(NT), 0, st, (const cx<T>*)g, (cx<T>*)vol, p.d_s, tw, N);          \
     return hipGetLastError();                                                                 \

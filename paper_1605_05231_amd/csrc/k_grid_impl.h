@@ -253,7 +253,7 @@ __device__ __forceinline__ cx<T> gather(const cx<T>* tile, const cx<T>* __restri
         read_row<T, J, MODE != 0, MODE == 1>(tile, ((l0 + a) * S + (l1 + b)) * S2 + l2, rv);
       } else {
         const int c0 = wrapK(first[0] + a, K), c1 = wrapK(first[1] + b, K);
-        const cx<T>* row = grid + ((int64_t)c0 * K + c1) * K;
+        const cx<T>* row = grid + (int64_t)c0 * grid_plane_of<T>(K) + (int64_t)c1 * K;
 #pragma unroll
         for (int c = 0; c < J; ++c) rv[c] = row[wrapK(first[2] + c, K)];
       }
@@ -330,7 +330,7 @@ __device__ __forceinline__ void interp_body(int64_t bx, const cx<T>* __restrict_
         if (idx < NE) {
           const int i2 = idx % S, i1 = (idx / S) % S, i0 = idx / (S * S);
           const int c0 = wrapK(o0 + i0, K), c1 = wrapK(o1 + i1, K), c2 = wrapK(o2 + i2, K);
-          v[k] = grid[((int64_t)c0 * K + c1) * K + c2];
+          v[k] = grid[(int64_t)c0 * grid_plane_of<T>(K) + (int64_t)c1 * K + c2];
         }
       }
 #pragma unroll
@@ -1131,7 +1131,8 @@ __device__ __forceinline__ void merge_body(int bx, const cx<T>* __restrict__ par
       if (hit[delta])
         for (int t = rng[2 * delta] + 1; t < rng[2 * delta + 1]; ++t)
           acc = cadd(acc, partials[t * PS + off[delta]]);
-    grid[((int64_t)(t0 * TILE + i0) * K + (t1 * TILE + i1)) * K + (t2 * TILE + i2)] = acc;
+    grid[(int64_t)(t0 * TILE + i0) * grid_plane_of<T>(K) + (int64_t)(t1 * TILE + i1) * K +
+         (t2 * TILE + i2)] = acc;
   }
 }
 
@@ -1261,7 +1262,8 @@ __global__ __launch_bounds__(1024) void k_merge_pairs(A args) {
           for (int t = rng[2 * delta] + 1; t < rng[2 * delta + 1]; ++t)
             acc[q] = cadd(acc[q], partials[t * PS + off[delta] + q]);
     float4* g4 = reinterpret_cast<float4*>(
-        grid + ((int64_t)(t0 * TILE + i0) * K + (t1 * TILE + i1)) * K + (t2 * TILE + i2));
+        grid + (int64_t)(t0 * TILE + i0) * grid_plane_of<float>(K) + (int64_t)(t1 * TILE + i1) * K +
+        (t2 * TILE + i2));
 #pragma unroll
     for (int q = 0; q < C; q += 2) g4[q >> 1] = make_float4(acc[q].x, acc[q].y, acc[q + 1].x, acc[q + 1].y);
   }

@@ -443,7 +443,7 @@ static int create(nufftct_plan** out, int64_t N, int64_t K, int J, int kernel, d
 
   // workspaces
   const size_t cxb = precision == NUFFTCT_FP32 ? 8 : 16;
-  p->grid_bytes = (size_t)K * K * K * cxb;
+  p->grid_bytes = ((size_t)K * (size_t)grid_plane(K, (int)cxb) * cxb + 255) / 256 * 256;
   p->tmp_bytes = (size_t)M * cxb;
   {
     hipError_t e = hipMalloc(&p->d_grid, p->grid_bytes);
@@ -907,14 +907,26 @@ int nufftct_stage(nufftct_plan* p, int stage, const void* in, void* out, int fla
   if ((stage == NUFFTCT_STAGE_RADIAL || stage == NUFFTCT_STAGE_RADIAL_ADJ) && p->n_r == 0)
     return fail(NUFFTCT_EINVAL, "plan has no radial lines (n_r = 0)");
   hipStream_t st = (hipStream_t)stream;
+  // the caller's grids are compact (K^3 cells); the plan's grid has planes
+  // grid_plane cells apart, which may include a pad
+  const size_t cxb = p->precision == NUFFTCT_FP32 ? 8 : 16;
+  const size_t plane = (size_t)p->K * p->K * cxb, pitch = (size_t)grid_plane(p->K, (int)cxb) * cxb;
+  const bool padded = pitch != plane;
+  const bool grid_in = stage == NUFFTCT_STAGE_INTERP || stage == NUFFTCT_STAGE_IFFT_CROP;
+  const bool grid_out = stage == NUFFTCT_STAGE_PAD_FFT || stage == NUFFTCT_STAGE_SPREAD;
   const void* src = in;
-  if (stage == NUFFTCT_STAGE_IFFT_CROP) {  // keep the caller's grid intact
-    HIP_TRY(hipMemcpyAsync(p->d_grid, in, p->grid_bytes, hipMemcpyDeviceToDevice, st));
+  void* dst = out;
+  if (grid_in && (padded || stage == NUFFTCT_STAGE_IFFT_CROP)) {
+    // (the inverse passes run in place: the caller's grid stays intact)
+    HIP_TRY(hipMemcpy2DAsync(p->d_grid, pitch, in, plane, plane, (size_t)p->K, hipMemcpyDeviceToDevice, st));
     src = p->d_grid;
   }
-  hipError_t e = p->precision == NUFFTCT_FP32 ? run_stage<float>(p, stage, src, out, flags, st, false)
-                                              : run_stage<double>(p, stage, src, out, flags, st, false);
+  if (grid_out && padded) dst = p->d_grid;
+  hipError_t e = p->precision == NUFFTCT_FP32 ? run_stage<float>(p, stage, src, dst, flags, st, false)
+                                              : run_stage<double>(p, stage, src, dst, flags, st, false);
   if (e != hipSuccess) return fail(NUFFTCT_EHIP, "launch failed: %s", hipGetErrorString(e));
+  if (dst != out)
+    HIP_TRY(hipMemcpy2DAsync(out, plane, p->d_grid, pitch, plane, (size_t)p->K, hipMemcpyDeviceToDevice, st));
   return NUFFTCT_OK;
 }
 

@@ -49,11 +49,21 @@ def wl(request):
     say(f"[fullsize] {W.name} oracle: {len(lines)} of {len(dirs)} lines, full {W.K}^3 transforms")
     Y = nufft.oversampled_spectrum(x.astype(np.complex128), prm)
     D = radial.forward(nufft.interpolate(Y, om, prm), W.n_r)
+    # sampled cells of the centred spectrum (the stage API's compact layout):
+    # random ones plus the grid's last planes, rows and columns
+    K = W.K
+    rs = np.random.default_rng(80)
+    cells = np.concatenate([rs.integers(0, K, (3000, 3)),
+                            np.stack([np.full(200, K - 1), rs.integers(0, K, 200), rs.integers(0, K, 200)], 1),
+                            np.stack([rs.integers(0, K, 200), np.full(200, K - 1), rs.integers(0, K, 200)], 1),
+                            np.stack([rs.integers(0, K, 200), rs.integers(0, K, 200), np.full(200, K - 1)], 1)])
+    Yc = Y[tuple(((cells + K // 2) % K).T)]  # centred cell j holds frequency j - K/2
     del Y
     rng = np.random.default_rng(78)
     d = rng.standard_normal(D.shape) + 1j * rng.standard_normal(D.shape)
     v = nufft.crop_scale(nufft.inverse_spectrum(nufft.spread(radial.adjoint(d, W.n_r), om, prm), prm), prm)
-    return {"W": W, "x": x, "dirs": dirs, "lines": lines, "D": D, "d": d, "v": v, "tiling": None}
+    return {"W": W, "x": x, "dirs": dirs, "lines": lines, "D": D, "d": d, "v": v, "tiling": None,
+            "cells": cells, "Yc": Yc}
 
 
 def _plan(pkg, W, dirs, dtype):
@@ -117,4 +127,39 @@ def test_dot_product_all_points(wl, prec):
     err = abs(lhs - rhs) / abs(lhs)
     say(f"[fullsize] {W.name} {prec}: dot test relative difference {err:.2e}")
     assert err < (1e-5 if prec == "f32" else 1e-12)
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_stage_chain_full_grid(wl, prec):
+    """The stage API at full size hands out compact K^3 grids while the plan's
+    own grid may pad its planes (512^2 planes are): the spectrum stage against
+    the oracle at sampled cells (last planes, rows and columns included), and
+    the stages chained through compact grids equal the fused operators bit for
+    bit."""
+    import torch
+    import paper_1605_05231_amd as pkg
+    W = wl["W"]
+    dtype = torch.complex64 if prec == "f32" else torch.complex128
+    plan = _plan(pkg, W, wl["dirs"], dtype)
+    x = to_dev(wl["x"], dtype)
+    g = torch.empty(W.K ** 3, dtype=dtype, device="cuda")
+    plan.stage(pkg.STAGE_PAD_FFT, x, g)
+    c = torch.from_numpy(wl["cells"]).cuda()
+    got = to_host(g.reshape(W.K, W.K, W.K)[c[:, 0], c[:, 1], c[:, 2]])
+    m = max_rel(got, wl["Yc"])
+    say(f"[fullsize] {W.name} {prec}: spectrum stage at {len(got)} cells, max err {m:.2e}")
+    assert m < (2e-6 if prec == "f32" else 1e-13)
+    G = torch.empty(W.M, dtype=dtype, device="cuda")
+    plan.stage(pkg.STAGE_INTERP, g, G)
+    D = torch.empty(W.M, dtype=dtype, device="cuda")
+    plan.stage(pkg.STAGE_RADIAL, G, D)
+    assert torch.equal(D, plan.forward(x).reshape(-1))
+    y = D.clone()
+    Gt = torch.empty(W.M, dtype=dtype, device="cuda")
+    plan.stage(pkg.STAGE_RADIAL_ADJ, y, Gt)
+    plan.stage(pkg.STAGE_SPREAD, Gt, g, deterministic=True)
+    v = torch.empty(W.N ** 3, dtype=dtype, device="cuda")
+    plan.stage(pkg.STAGE_IFFT_CROP, g, v)
+    assert torch.equal(v, plan.adjoint(y, deterministic=True).reshape(-1))
     plan.close()
