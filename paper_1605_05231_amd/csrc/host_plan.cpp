@@ -6,6 +6,7 @@
 #include "host_plan.h"
 
 #include <algorithm>
+#include <utility>
 #include <cmath>
 #include <thread>
 
@@ -61,12 +62,14 @@ void point_omega(const BinParams& p, const std::vector<double>& geom, int64_t i,
 //     c = (l0 S + l1) S2 + l2; even cells first, then odd ones (a wave's
 //     row reads then share one alignment), each class dealt round-robin over
 //     its 16 residues mod 32.  FP64 interpolation uses the spreading order.
-// With `twins` (FP32), each bin is first put in the order of its points'
-// cells and frequencies, so that the two points of a frequency sampled twice
-// (as lines in opposite directions sample it) become one pair; the pairs
-// whose frequencies agree to 1e-12 (relative) then come first in both
+// With `twins` (FP32), the two points of a frequency sampled twice (as lines
+// in opposite directions sample it: FP64 frequencies that agree to 1e-12,
+// relative, and one first tap cell) are linked, kept next to each other in
+// the bin and in one task, and paired; their pairs come first in both
 // orders: one evaluation of the weights serves both points in spreading, and
-// one interpolation both outputs.
+// one interpolation both outputs.  Tasks and deals otherwise keep the
+// points' own order (cell-sorted tasks and deals measured up to 4x slower in
+// spreading: neighbouring lanes and waves then add to the same cells).
 void build_bins(const BinParams& p, const std::vector<double>& geom, Binning& B) {
   const int64_t M = p.M;
   const int nb = p.nb, T = p.tile, J = p.J;
@@ -108,10 +111,12 @@ void build_bins(const BinParams& p, const std::vector<double>& geom, Binning& B)
     std::vector<int64_t> pos(off.begin(), off.end() - 1);
     for (int64_t i = 0; i < M; ++i) B.perm_s[pos[key[i]]++] = (int32_t)i;
   }
+  // twins (FP32): within each bin, points put in the order of their first tap
+  // cells and frequencies quantised to 2^-30 make the two samples of one
+  // frequency neighbours; those whose FP64 frequencies agree to 1e-12
+  // (relative) and share the first cell are linked.
+  std::vector<int32_t> twin_of(p.twins ? M : 0, -1);
   if (p.twins) {
-    // each bin in the order of its points' first tap cells, then of their
-    // frequencies quantised to 2^-30: the two points of a frequency sampled
-    // twice become neighbours, in one task and one pair
     struct QKey {
       uint16_t cell;
       int64_t q[3];
@@ -119,6 +124,7 @@ void build_bins(const BinParams& p, const std::vector<double>& geom, Binning& B)
     };
     parallel(nbins, [&](int64_t a, int64_t b) {
       std::vector<QKey> qk;
+      std::vector<int32_t> order;
       for (int64_t bin = a; bin < b; ++bin) {
         const int64_t s = off[bin], n = off[bin + 1] - s;
         qk.resize(n);
@@ -136,7 +142,52 @@ void build_bins(const BinParams& p, const std::vector<double>& geom, Binning& B)
             if (x.q[c] != y.q[c]) return x.q[c] < y.q[c];
           return false;
         });
-        for (int64_t i = 0; i < n; ++i) B.perm_s[s + i] = qk[i].pt;
+        for (int64_t i = 0; i + 1 < n;) {
+          const int32_t x = qk[i].pt, y = qk[i + 1].pt;
+          if (qk[i].cell == qk[i + 1].cell) {
+            double oa[3], ob[3];
+            point_omega(p, geom, x, oa);
+            point_omega(p, geom, y, ob);
+            double dmax = 0.0, amax = 1.0;
+            for (int c = 0; c < 3; ++c) {
+              dmax = std::max(dmax, std::fabs(oa[c] - ob[c]));
+              amax = std::max(amax, std::fabs(oa[c]));
+            }
+            if (dmax <= 1e-12 * amax) {
+              twin_of[x] = y;
+              twin_of[y] = x;
+              i += 2;
+              continue;
+            }
+          }
+          ++i;
+        }
+        // the bin's units (a twin pair, or a point) in a fixed pseudo-random
+        // order, each twin pair kept together: tasks cut from it hold even
+        // shares of every cell.  (Units in point order would gather most of
+        // the coincident omega = 0 samples into the bin's last task: twins
+        // pulled next to their lower-index partner empty the tail of
+        // everything else.)
+        order.clear();
+        for (int64_t i = 0; i < n; ++i) {
+          const int32_t pt = B.perm_s[s + i], tw = twin_of[pt];
+          if (tw < 0 || pt < tw) order.push_back(pt);
+        }
+        auto mix = [](uint32_t x) {  // an invertible 32-bit integer mix
+          x ^= x >> 16;
+          x *= 0x7feb352dU;
+          x ^= x >> 15;
+          x *= 0x846ca68bU;
+          x ^= x >> 16;
+          return x;
+        };
+        std::sort(order.begin(), order.end(),
+                  [&](int32_t x, int32_t y) { return mix((uint32_t)x) < mix((uint32_t)y); });
+        int64_t o = s;
+        for (const int32_t pt : order) {
+          B.perm_s[o++] = pt;
+          if (twin_of[pt] >= 0) B.perm_s[o++] = twin_of[pt];
+        }
       }
     });
   }
@@ -145,23 +196,32 @@ void build_bins(const BinParams& p, const std::vector<double>& geom, Binning& B)
   for (int64_t b = 0; b < nbins; ++b) {
     B.bin_tasks[b] = (int32_t)B.tasks.size();
     const int64_t s = off[b], e = off[b + 1];
-    for (int64_t q = s; q < e; q += p.max_pts) {
+    for (int64_t q = s; q < e;) {
       TileTask t;
       t.bin = (int32_t)b;
       t.start = (int32_t)q;
-      t.count = (int32_t)std::min<int64_t>(p.max_pts, e - q);
+      int64_t n = std::min<int64_t>(p.max_pts, e - q);
+      // a task never separates twins
+      if (p.twins && q + n < e && twin_of[B.perm_s[q + n - 1]] == B.perm_s[q + n]) --n;
+      t.count = (int32_t)n;
       t.npairs = 0;
       t.ntwins = 0;
       B.tasks.push_back(t);
+      q += n;
     }
   }
   B.bin_tasks[nbins] = (int32_t)B.tasks.size();
   B.perm = B.perm_s;
   // Reorder pts[0..n) by residue: classes of residues r = cls, cls + step, ...
   // in turn, each dealt round-robin over its residues.
+  // With `cell` (spreading), each residue's points are first put in turns
+  // over their first cells (one point of every cell, then a second of every
+  // cell that has one, ...), so that the two points a wave takes from one
+  // residue rarely share a cell: lanes adding to the same cell in one LDS
+  // atomic are serialised.
   struct Deal {
-    std::vector<int32_t> tmp, bucket, cnt = std::vector<int32_t>(33), fill;
-    void run(int32_t* pts, int n, const uint8_t* res, int step) {
+    std::vector<int32_t> tmp, bucket, cnt = std::vector<int32_t>(33), fill, seg;
+    void run(int32_t* pts, int n, const uint8_t* res, int step, const uint16_t* cell = nullptr) {
       std::fill(cnt.begin(), cnt.end(), 0);
       for (int i = 0; i < n; ++i) cnt[res[pts[i]] + 1]++;
       for (int r = 0; r < 32; ++r) cnt[r + 1] += cnt[r];
@@ -169,6 +229,26 @@ void build_bins(const BinParams& p, const std::vector<double>& geom, Binning& B)
       bucket.resize(n);
       fill.assign(cnt.begin(), cnt.end() - 1);
       for (int i = 0; i < n; ++i) bucket[fill[res[tmp[i]]]++] = tmp[i];
+      if (cell)
+        for (int r = 0; r < 32; ++r) {
+          int32_t* b = bucket.data() + cnt[r];
+          const int m = cnt[r + 1] - cnt[r];
+          if (m < 2) continue;
+          std::stable_sort(b, b + m, [&](int32_t x, int32_t y) { return cell[x] < cell[y]; });
+          if (step == 2) continue;  // (interpolation: kept in cell order)
+          seg.clear();
+          std::vector<std::pair<int, int>> groups;  // (start, size) of each cell's run
+          for (int i = 0; i < m;) {
+            int j = i;
+            while (j < m && cell[b[j]] == cell[b[i]]) ++j;
+            groups.push_back({i, j - i});
+            i = j;
+          }
+          for (int k = 0; (int)seg.size() < m; ++k)
+            for (const auto& g : groups)
+              if (k < g.second) seg.push_back(b[g.first + k]);
+          std::copy(seg.begin(), seg.end(), b);
+        }
       int o = 0;
       for (int cls = 0; cls < step; ++cls) {
         int left = 0;
@@ -214,68 +294,73 @@ void build_bins(const BinParams& p, const std::vector<double>& geom, Binning& B)
   };
   parallel((int64_t)B.tasks.size(), [&](int64_t a, int64_t b) {
     Deal d;
-    std::vector<int32_t> sorted, first_of, singles, idx, twin_first, other_first, rest;
+    std::vector<int32_t> sorted, singles, loose, idx, rest;
+    std::vector<std::pair<int32_t, int32_t>> twin_pairs, other_pairs;
     std::vector<uint8_t> res_pair;
+    std::vector<uint16_t> cell_pair;
     for (int64_t k = a; k < b; ++k) {
       TileTask& t = B.tasks[k];
       int32_t* ps = B.perm_s.data() + t.start;
       if (!pair_spread) {  // no paired spreading: points dealt one by one
-        d.run(ps, t.count, res_s.data(), 1);
+        d.run(ps, t.count, res_s.data(), 1, lcell.data());
         t.npairs = 0;
         d.run(B.perm.data() + t.start, t.count, pairs ? res_i.data() : res_s.data(), pairs ? 2 : 1);
         continue;
       }
-      // pair the points of each first tap cell (in the bin's order within it)
+      // pair the points of each first tap cell: twins (adjacent in the task's
+      // order, so also after the stable sort by cell) with each other, the
+      // other points of the cell in their order; the lists then go back to
+      // point order, so that points dealt to neighbouring lanes and waves
+      // rarely share a cell
       sorted.assign(ps, ps + t.count);
       std::stable_sort(sorted.begin(), sorted.end(),
                        [&](int32_t x, int32_t y) { return lcell[x] < lcell[y]; });
-      first_of.clear();
+      twin_pairs.clear();
+      other_pairs.clear();
       singles.clear();
       for (int i = 0; i < t.count;) {
         int j = i;
         while (j < t.count && lcell[sorted[j]] == lcell[sorted[i]]) ++j;
-        for (int q = i; q + 1 < j; q += 2) {
-          first_of.push_back(q);  // pair (sorted[q], sorted[q + 1])
+        loose.clear();
+        for (int q = i; q < j;) {
+          if (p.twins && q + 1 < j && twin_of[sorted[q]] == sorted[q + 1]) {
+            twin_pairs.push_back({sorted[q], sorted[q + 1]});
+            q += 2;
+          } else {
+            loose.push_back(sorted[q++]);
+          }
         }
-        if ((j - i) & 1) singles.push_back(sorted[j - 1]);
+        for (size_t q = 0; q + 1 < loose.size(); q += 2) other_pairs.push_back({loose[q], loose[q + 1]});
+        if (loose.size() & 1) singles.push_back(loose.back());
         i = j;
       }
-      // with `twins`, the pairs whose two frequencies agree to 1e-12
-      // (relative) come first, in both orders
-      auto is_twin = [&](int32_t x, int32_t y) {
-        double oa[3], ob[3];
-        point_omega(p, geom, x, oa);
-        point_omega(p, geom, y, ob);
-        double dmax = 0.0, amax = 1.0;
-        for (int c = 0; c < 3; ++c) {
-          dmax = std::max(dmax, std::fabs(oa[c] - ob[c]));
-          amax = std::max(amax, std::fabs(oa[c]));
-        }
-        return dmax <= 1e-12 * amax;
+      auto by_first = [](const std::pair<int32_t, int32_t>& x, const std::pair<int32_t, int32_t>& y) {
+        return x.first < y.first;
       };
-      twin_first.clear();
-      other_first.clear();
-      for (int32_t q : first_of)
-        (p.twins && is_twin(sorted[q], sorted[q + 1]) ? twin_first : other_first).push_back(q);
-      const int nt = (int)twin_first.size(), np = (int)first_of.size();
+      std::sort(twin_pairs.begin(), twin_pairs.end(), by_first);
+      std::sort(other_pairs.begin(), other_pairs.end(), by_first);
+      std::sort(singles.begin(), singles.end());
+      const int nt = (int)twin_pairs.size(), np = nt + (int)other_pairs.size();
       // spreading order: twin pairs, other pairs, single points, each dealt
       // over the residues of their first cells
       int32_t* o = ps;
-      for (const std::vector<int32_t>* set : {&twin_first, &other_first}) {
+      for (const auto* set : {&twin_pairs, &other_pairs}) {
         const int n = (int)set->size();
         idx.resize(n);
         res_pair.resize(n);
+        cell_pair.resize(n);
         for (int q = 0; q < n; ++q) {
           idx[q] = q;
-          res_pair[q] = res_s[sorted[(*set)[q]]];
+          res_pair[q] = res_s[(*set)[q].first];
+          cell_pair[q] = lcell[(*set)[q].first];
         }
-        d.run(idx.data(), n, res_pair.data(), 1);
+        d.run(idx.data(), n, res_pair.data(), 1, cell_pair.data());
         for (int q = 0; q < n; ++q) {
-          *o++ = sorted[(*set)[idx[q]]];
-          *o++ = sorted[(*set)[idx[q]] + 1];
+          *o++ = (*set)[idx[q]].first;
+          *o++ = (*set)[idx[q]].second;
         }
       }
-      d.run(singles.data(), (int)singles.size(), res_s.data(), 1);
+      d.run(singles.data(), (int)singles.size(), res_s.data(), 1, lcell.data());
       std::copy(singles.begin(), singles.end(), o);
       t.npairs = np;
       t.ntwins = nt;
@@ -292,13 +377,15 @@ void build_bins(const BinParams& p, const std::vector<double>& geom, Binning& B)
         idx[q] = q;
         res_pair[q] = res_i[ps[2 * q]];
       }
-      d.run(idx.data(), nt, res_pair.data(), 2);
+      cell_pair.resize(nt);
+      for (int q = 0; q < nt; ++q) cell_pair[q] = lcell[ps[2 * q]];
+      d.run(idx.data(), nt, res_pair.data(), 2, cell_pair.data());
       for (int q = 0; q < nt; ++q) {
         pi[2 * q] = ps[2 * idx[q]];
         pi[2 * q + 1] = ps[2 * idx[q] + 1];
       }
       rest.assign(ps + 2 * nt, ps + t.count);
-      d.run(rest.data(), (int)rest.size(), res_i.data(), 2);
+      d.run(rest.data(), (int)rest.size(), res_i.data(), 2, lcell.data());
       std::copy(rest.begin(), rest.end(), pi + 2 * nt);
     }
   });
