@@ -142,9 +142,20 @@ void build_bins(const BinParams& p, const std::vector<double>& geom, Binning& B)
             if (x.q[c] != y.q[c]) return x.q[c] < y.q[c];
           return false;
         });
-        for (int64_t i = 0; i + 1 < n;) {
-          const int32_t x = qk[i].pt, y = qk[i + 1].pt;
-          if (qk[i].cell == qk[i + 1].cell) {
+        // runs of one cell and quantised frequency (in point order); a run of
+        // k points links its first and second halves, point m with point
+        // m + k/2: a twin pair for k = 2, and for the frequency every line
+        // samples (omega = 0) the samples of opposite lines
+        auto same_q = [&](int64_t x, int64_t y) {
+          return qk[x].cell == qk[y].cell && qk[x].q[0] == qk[y].q[0] && qk[x].q[1] == qk[y].q[1] &&
+                 qk[x].q[2] == qk[y].q[2];
+        };
+        for (int64_t i = 0; i < n;) {
+          int64_t j = i + 1;
+          while (j < n && same_q(i, j)) ++j;
+          const int64_t h = (j - i) / 2;
+          for (int64_t m = 0; m < h; ++m) {
+            const int32_t x = qk[i + m].pt, y = qk[i + m + h].pt;
             double oa[3], ob[3];
             point_omega(p, geom, x, oa);
             point_omega(p, geom, y, ob);
@@ -156,33 +167,21 @@ void build_bins(const BinParams& p, const std::vector<double>& geom, Binning& B)
             if (dmax <= 1e-12 * amax) {
               twin_of[x] = y;
               twin_of[y] = x;
-              i += 2;
-              continue;
             }
           }
-          ++i;
+          i = j;
         }
-        // the bin's units (a twin pair, or a point) in a fixed pseudo-random
-        // order, each twin pair kept together: tasks cut from it hold even
-        // shares of every cell.  (Units in point order would gather most of
-        // the coincident omega = 0 samples into the bin's last task: twins
-        // pulled next to their lower-index partner empty the tail of
-        // everything else.)
+        // the bin's units (a twin pair, or a point) in the order of their
+        // first point: tasks cut from it hold runs of neighbouring lines and
+        // of their opposites (whose values share cache lines).  (Coincident
+        // samples linked in point order instead of by halves would leave
+        // most of the omega = 0 samples of the bin's second half together at
+        // its end, in one task whose LDS atomics on that cell serialise.)
         order.clear();
         for (int64_t i = 0; i < n; ++i) {
           const int32_t pt = B.perm_s[s + i], tw = twin_of[pt];
           if (tw < 0 || pt < tw) order.push_back(pt);
         }
-        auto mix = [](uint32_t x) {  // an invertible 32-bit integer mix
-          x ^= x >> 16;
-          x *= 0x7feb352dU;
-          x ^= x >> 15;
-          x *= 0x846ca68bU;
-          x ^= x >> 16;
-          return x;
-        };
-        std::sort(order.begin(), order.end(),
-                  [&](int32_t x, int32_t y) { return mix((uint32_t)x) < mix((uint32_t)y); });
         int64_t o = s;
         for (const int32_t pt : order) {
           B.perm_s[o++] = pt;
