@@ -201,27 +201,29 @@ template <typename T>
 constexpr int interp_pitch(int S) { return sizeof(T) == 4 ? S + (S & 1) : S; }
 
 // Read J consecutive complex values of a staged row starting at element rs.
-// PAIRS (FP32 only): aligned 16-byte reads of value pairs, EVEN tells the
-// parity of rs (even: J/2 pair reads; odd: one 8-byte read, then pairs),
-// halving the LDS instructions of the gather.
-template <typename T, int J, bool PAIRS, bool EVEN>
+template <typename T, int J>
 __device__ __forceinline__ void read_row(const cx<T>* tile, int rs, cx<T> (&v)[J]) {
-  if constexpr (PAIRS) {
-    static_assert(sizeof(T) == 4, "pair reads are for FP32 complex values");
-    const float4* q = reinterpret_cast<const float4*>(tile);
-    constexpr int k0 = EVEN ? 0 : 1;
-    if constexpr (!EVEN) v[0] = tile[rs];
 #pragma unroll
-    for (int k = k0; k + 1 < J; k += 2) {
-      const float4 w = q[(rs + k) >> 1];
-      v[k] = cx<T>{w.x, w.y};
-      v[k + 1] = cx<T>{w.z, w.w};
-    }
-    if constexpr (((J - k0) & 1) != 0) v[J - 1] = tile[rs + J - 1];
-  } else {
+  for (int k = 0; k < J; ++k) v[k] = tile[rs + k];
+}
+
+// The same row read as aligned 16-byte pairs (FP32 only; the row pitch is
+// even), halving the LDS instructions of the gather: rs the row's first
+// element (read singly when odd, as is an odd tail), h the index of the
+// first aligned pair at or after it, EVEN the parity of rs.
+template <typename T, int J, bool EVEN>
+__device__ __forceinline__ void read_row_pairs(const cx<T>* tile, int rs, int h, cx<T> (&v)[J]) {
+  static_assert(sizeof(T) == 4, "pair reads are for FP32 complex values");
+  const float4* q = reinterpret_cast<const float4*>(tile);
+  constexpr int k0 = EVEN ? 0 : 1;
+  if constexpr (!EVEN) v[0] = tile[rs];
 #pragma unroll
-    for (int k = 0; k < J; ++k) v[k] = tile[rs + k];
+  for (int k = k0; k + 1 < J; k += 2) {
+    const float4 w = q[h + (k - k0) / 2];
+    v[k] = cx<T>{w.x, w.y};
+    v[k + 1] = cx<T>{w.z, w.w};
   }
+  if constexpr (((J - k0) & 1) != 0) v[J - 1] = tile[rs + J - 1];
 }
 
 template <typename T, int J, bool CW>
@@ -240,6 +242,12 @@ __device__ __forceinline__ cx<T> gather(const cx<T>* tile, const cx<T>* __restri
                                         const T (&w0r)[J], const T (&w0i)[J], const T (&w1r)[J],
                                         const T (&w1i)[J], const T (&w2r)[J], const T (&w2i)[J]) {
   cx<T> acc = {0, 0};
+  // pair reads: the first tap's staged element and the index of the first
+  // 16-byte pair at or after it; with S2 even, every other row of the
+  // footprint starts a constant number of pairs further, so the reads'
+  // addresses differ only by immediate offsets
+  const int rs0 = (l0 * S + l1) * S2 + l2;
+  const int h0 = (rs0 + (MODE == 2 ? 1 : 0)) >> 1;
   // the outermost tap loop stays rolled: full unrolling lets the compiler
   // hoist every row read of a point and spill
 #pragma unroll 1
@@ -249,8 +257,12 @@ __device__ __forceinline__ cx<T> gather(const cx<T>* tile, const cx<T>* __restri
     for (int b = 0; b < J; ++b) {
       cx<T> acc_b = {0, 0};
       cx<T> rv[J];
-      if (MODE != 0 || inside) {
-        read_row<T, J, MODE != 0, MODE == 1>(tile, ((l0 + a) * S + (l1 + b)) * S2 + l2, rv);
+      if constexpr (MODE != 0) {
+        static_assert(S2 % 2 == 0, "pair reads need an even row pitch");
+        const int row = (a * S + b) * S2;
+        read_row_pairs<T, J, MODE == 1>(tile, rs0 + row, h0 + (a * S + b) * (S2 / 2), rv);
+      } else if (inside) {
+        read_row<T, J>(tile, ((l0 + a) * S + (l1 + b)) * S2 + l2, rv);
       } else {
         const int c0 = wrapK(first[0] + a, K), c1 = wrapK(first[1] + b, K);
         const cx<T>* row = grid + (int64_t)c0 * grid_plane_of<T>(K) + (int64_t)c1 * K;
