@@ -311,6 +311,58 @@ __host__ __device__ inline int part_offset(int q0, int q1, int q2, int tile, int
 // ---------------------------------------------------------------------------
 // (the kernels below are device bodies taking their block index, wrapped by
 // one-plan kernels here and by the batch kernels of k_batch_impl.h)
+// Stage the S^3 halo tile at grid cell (o0, o1, o2) into LDS (rows of pitch
+// S2): a thread's elements idx = tid + k NT, all CH loads in flight before
+// their LDS writes, coordinates stepped by NT's own digits in base S (no
+// division per element).  WRAP: the halo crosses the grid's end, so every
+// coordinate wraps; otherwise the elements' grid offsets are stepped too.
+template <typename T, int S, int S2, int NT, int CH, bool WRAP>
+__device__ __forceinline__ void stage_halo(cx<T>* tile, const cx<T>* __restrict__ grid, int K,
+                                           int o0, int o1, int o2) {
+  constexpr int NE = S * S * S;
+  constexpr int D0 = NT / (S * S), D1 = (NT / S) % S, D2 = NT % S;
+  const int P = (int)grid_plane_of<T>(K);
+  const cx<T>* gt = grid + (int64_t)o0 * P + (int64_t)o1 * K + o2;
+#pragma unroll 1
+  for (int i = threadIdx.x; i < NE; i += CH * NT) {
+    cx<T> v[CH];
+    int lds[CH];
+    int i2 = i % S, i1 = (i / S) % S, i0 = i / (S * S);
+    int go = i0 * P + i1 * K + i2, li = (i0 * S + i1) * S2 + i2;
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+      lds[k] = li;
+      if (i + k * NT < NE) {
+        if constexpr (!WRAP) {
+          v[k] = gt[go];
+        } else {
+          const int c0 = wrapK(o0 + i0, K), c1 = wrapK(o1 + i1, K), c2 = wrapK(o2 + i2, K);
+          v[k] = grid[(int64_t)c0 * P + (int64_t)c1 * K + c2];
+        }
+      }
+      i2 += D2;
+      go += D0 * P + D1 * K + D2;
+      li += (D0 * S + D1) * S2 + D2;
+      if (i2 >= S) {
+        i2 -= S;
+        ++i1;
+        go += K - S;
+        li += S2 - S;
+      }
+      i1 += D1;
+      if (i1 >= S) {
+        i1 -= S;
+        ++i0;
+        go += P - S * K;
+      }
+      i0 += D0;
+    }
+#pragma unroll
+    for (int k = 0; k < CH; ++k)
+      if (i + k * NT < NE) tile[lds[k]] = v[k];
+  }
+}
+
 template <typename T, int J, int TILE, bool CW, int DEG>
 __device__ __forceinline__ void interp_body(int64_t bx, const cx<T>* __restrict__ grid,
                                             cx<T>* __restrict__ out,
@@ -336,27 +388,11 @@ __device__ __forceinline__ void interp_body(int64_t bx, const cx<T>* __restrict_
     // 16^3 tiles; 8 per round measured 10 % slower at c3)
     constexpr int NE = S * S * S;
     constexpr int CH = (NE + NT_INTERP - 1) / NT_INTERP < 20 ? (NE + NT_INTERP - 1) / NT_INTERP : 20;
-#pragma unroll 1
-    for (int i = threadIdx.x; i < NE; i += CH * NT_INTERP) {
-      cx<T> v[CH];
-#pragma unroll
-      for (int k = 0; k < CH; ++k) {
-        const int idx = i + k * NT_INTERP;
-        if (idx < NE) {
-          const int i2 = idx % S, i1 = (idx / S) % S, i0 = idx / (S * S);
-          const int c0 = wrapK(o0 + i0, K), c1 = wrapK(o1 + i1, K), c2 = wrapK(o2 + i2, K);
-          v[k] = grid[(int64_t)c0 * grid_plane_of<T>(K) + (int64_t)c1 * K + c2];
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < CH; ++k) {
-        const int idx = i + k * NT_INTERP;
-        if (idx < NE) {
-          const int i2 = idx % S, i1 = (idx / S) % S, i0 = idx / (S * S);
-          tile[(i0 * S + i1) * S2 + i2] = v[k];
-        }
-      }
-    }
+    const bool edge = o0 + S > K || o1 + S > K || o2 + S > K;
+    if (edge)
+      stage_halo<T, S, S2, NT_INTERP, CH, true>(tile, grid, K, o0, o1, o2);
+    else
+      stage_halo<T, S, S2, NT_INTERP, CH, false>(tile, grid, K, o0, o1, o2);
   }
   __syncthreads();
   // Units of the task's interpolation order: unit u < ntwins is the pair of
