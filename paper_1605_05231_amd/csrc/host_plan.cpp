@@ -301,9 +301,42 @@ void build_bins(const BinParams& p, const std::vector<double>& geom, Binning& B)
       TileTask& t = B.tasks[k];
       int32_t* ps = B.perm_s.data() + t.start;
       if (!pair_spread) {  // no paired spreading: points dealt one by one
+        int32_t* pi = B.perm.data() + t.start;  // (still the bin's order)
+        if (p.twins) {
+          // interpolation order: the task's twin pairs (adjacent in the bin's
+          // order), then every other point
+          twin_pairs.clear();
+          rest.clear();
+          for (int i = 0; i < t.count;) {
+            if (i + 1 < t.count && twin_of[pi[i]] == pi[i + 1]) {
+              twin_pairs.push_back({pi[i], pi[i + 1]});
+              i += 2;
+            } else {
+              rest.push_back(pi[i++]);
+            }
+          }
+          const int nt = (int)twin_pairs.size();
+          idx.resize(nt);
+          res_pair.resize(nt);
+          cell_pair.resize(nt);
+          for (int q = 0; q < nt; ++q) {
+            idx[q] = q;
+            res_pair[q] = res_i[twin_pairs[q].first];
+            cell_pair[q] = lcell[twin_pairs[q].first];
+          }
+          d.run(idx.data(), nt, res_pair.data(), 2, cell_pair.data());
+          for (int q = 0; q < nt; ++q) {
+            pi[2 * q] = twin_pairs[idx[q]].first;
+            pi[2 * q + 1] = twin_pairs[idx[q]].second;
+          }
+          d.run(rest.data(), (int)rest.size(), res_i.data(), 2, lcell.data());
+          std::copy(rest.begin(), rest.end(), pi + 2 * nt);
+          t.ntwins = nt;
+        } else {
+          d.run(pi, t.count, pairs ? res_i.data() : res_s.data(), pairs ? 2 : 1);
+        }
         d.run(ps, t.count, res_s.data(), 1, lcell.data());
         t.npairs = 0;
-        d.run(B.perm.data() + t.start, t.count, pairs ? res_i.data() : res_s.data(), pairs ? 2 : 1);
         continue;
       }
       // pair the points of each first tap cell: twins (adjacent in the task's

@@ -362,8 +362,9 @@ static int create(nufftct_plan** out, int64_t N, int64_t K, int J, int kernel, d
     bp.pair_spread = bp.fp32 && kernel != NUFFTCT_KERNEL_MINMAX_KB;
     // the FP32 interpolation serves the two points of a frequency sampled
     // twice with one evaluation (their frequencies agree to FP64 rounding,
-    // far below the FP32 result's precision)
-    bp.twins = bp.pair_spread;
+    // far below the FP32 result's precision); the Kaiser-Bessel spreading
+    // also spreads such a pair with one set of weights
+    bp.twins = bp.fp32;
     hostplan::build_bins(bp, g, B);
     p->ntasks = (int64_t)B.tasks.size();
     {
@@ -489,27 +490,30 @@ struct StageTimer {
   hipStream_t st;
   int stage;
   hipEvent_t a = nullptr, b = nullptr;
+  // (timing is best effort: a stage whose events cannot be created or
+  // recorded goes untimed, and the launch itself is unaffected)
   StageTimer(nufftct_plan* p_, hipStream_t st_, int stage_) : p(p_), st(st_), stage(stage_) {
-    if (p->timing) {
-      hipEventCreate(&a);
-      hipEventCreate(&b);
-      hipEventRecord(a, st);
-    }
-  }
-  void restart() {
-    if (p->timing && a) hipEventRecord(a, st);
+    if (!p->timing) return;
+    if (hipEventCreate(&a) != hipSuccess) a = nullptr;
+    if (a && hipEventCreate(&b) != hipSuccess) b = nullptr;
+    if (a && b && hipEventRecord(a, st) == hipSuccess) return;
+    release();
   }
   void done() {
-    if (p->timing && a) {
-      hipEventRecord(b, st);
+    if (!a || !b) return;
+    if (hipEventRecord(b, st) == hipSuccess) {
       p->events.push_back({a, b, stage});
       a = b = nullptr;
+    } else {
+      release();
     }
   }
-  ~StageTimer() {
+  void release() {
     if (a) hipEventDestroy(a);
     if (b) hipEventDestroy(b);
+    a = b = nullptr;
   }
+  ~StageTimer() { release(); }
 };
 
 // prune: grid cells outside the taps' ball are neither produced nor read

@@ -129,11 +129,11 @@ def check_binning(o, om, pair_spread):
             1.0, np.max(np.abs(om[p[:, 0]]), axis=1))
         n_same += int(same.sum())
         assert 2 * ntwins <= count and (o["twins"] or ntwins == 0)
-        assert np.all(same[:ntwins])  # twins first
         tw = seg_i[:2 * ntwins].reshape(-1, 2)
         assert np.array_equal(first[tw[:, 0]], first[tw[:, 1]])
         assert np.all(np.abs(om[tw[:, 0]] - om[tw[:, 1]]) <= 1e-12 * np.maximum(1.0, np.abs(om[tw[:, 0]])))
-        if o["twins"]:
+        if o["twins"] and pair_spread:
+            assert np.all(same[:ntwins])  # twins first
             assert ntwins == same.sum() and not np.any(same[ntwins:])
             want = {frozenset(q) for q in p[same].tolist()}
             assert {frozenset(q) for q in tw.tolist()} == want
@@ -163,6 +163,11 @@ def test_first_taps_and_binning_radial(harness, case):
                 max_pts=max_pts)
         assert np.array_equal(o["first"], oracle_first(om, K, J)), name
         n_twins, _ = check_binning(o, om, True)
+        # without paired spreading (min-max weights) the interpolation still
+        # takes the same twins
+        o2 = run(harness, K=K, J=J, N=N, geom=dirs, n_r=n_r, radial_plan=True, tile=tile,
+                 max_pts=max_pts, pair_spread=False, twins=True)
+        assert check_binning(o2, om, False)[0] == n_twins
         # lines (phi, theta) and (phi + pi, pi - theta) sample the same
         # frequencies in opposite order; the twins that can share an
         # interpolation are those whose first taps agree (a tie can split
