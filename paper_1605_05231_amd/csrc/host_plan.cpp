@@ -329,12 +329,26 @@ void build_bins(const BinParams& p, const std::vector<double>& geom, Binning& B)
             pi[2 * q] = twin_pairs[idx[q]].first;
             pi[2 * q + 1] = twin_pairs[idx[q]].second;
           }
+          // spreading order: the twin pairs (one set of weights each), then
+          // the rest, each dealt over the residues of their first cells
+          for (int q = 0; q < nt; ++q) {
+            idx[q] = q;
+            res_pair[q] = res_s[twin_pairs[q].first];
+          }
+          d.run(idx.data(), nt, res_pair.data(), 1, cell_pair.data());
+          for (int q = 0; q < nt; ++q) {
+            ps[2 * q] = twin_pairs[idx[q]].first;
+            ps[2 * q + 1] = twin_pairs[idx[q]].second;
+          }
           d.run(rest.data(), (int)rest.size(), res_i.data(), 2, lcell.data());
           std::copy(rest.begin(), rest.end(), pi + 2 * nt);
+          d.run(rest.data(), (int)rest.size(), res_s.data(), 1, lcell.data());
+          std::copy(rest.begin(), rest.end(), ps + 2 * nt);
           t.ntwins = nt;
-        } else {
-          d.run(pi, t.count, pairs ? res_i.data() : res_s.data(), pairs ? 2 : 1);
+          t.npairs = nt;
+          continue;
         }
+        d.run(pi, t.count, pairs ? res_i.data() : res_s.data(), pairs ? 2 : 1);
         d.run(ps, t.count, res_s.data(), 1, lcell.data());
         t.npairs = 0;
         continue;

@@ -778,8 +778,9 @@ __device__ __forceinline__ void spread_task(int64_t task_id, const cx<T>* __rest
   // FP32 with real weights: both points' contributions to a cell summed
   // before one atomic; otherwise (min-max weights, or FP64, whose register
   // budget it would exceed) the points of a unit are spread one by one.
-  // The first ntwins pairs sample one frequency twice: their weights are
-  // evaluated once and spread the sum of the two values.
+  // The first ntwins pairs (FP32, either weights) sample one frequency
+  // twice: their weights are evaluated once and spread the sum of the two
+  // values.
   constexpr bool PAIRED = !CW && sizeof(T) == 4;
   const int np = tk.npairs, nunits = tk.count - np, nt = tk.ntwins;
   cx<T>* dst = partials + task_id * (int64_t)part_stride(TILE, R);
@@ -829,7 +830,7 @@ __device__ __forceinline__ void spread_task(int64_t task_id, const cx<T>* __rest
       nxt = fetch_point(g, perm, tk.start + e);
       vnxt = in[nxt.p];
       vnxt2 = cx<T>{0, 0};
-      if (PAIRED && u < nt) {
+      if (sizeof(T) == 4 && u < nt) {
         nxt2.p = perm[tk.start + e + 1];  // (a twin's geometry is the first point's)
         vnxt2 = in[nxt2.p];
       } else if (PAIRED && u < np) {
@@ -845,8 +846,9 @@ __device__ __forceinline__ void spread_task(int64_t task_id, const cx<T>* __rest
       PtRaw cur = nxt, cur2 = nxt2;
       cx<T> v = vnxt, v2 = vnxt2;
       const bool pair = u < np;
+      const bool twin = sizeof(T) == 4 && u < nt;
       if (u + NT_SPREAD < nunits) fetch_unit(u + NT_SPREAD);
-      if (!PAIRED && pair) {
+      if (!PAIRED && pair && !twin) {
         cur2 = fetch_point(g, perm, tk.start + 2 * u + 1);
         v2 = in[cur2.p];
       }
@@ -868,7 +870,6 @@ __device__ __forceinline__ void spread_task(int64_t task_id, const cx<T>* __rest
         const bool nz = v.x != (T)0 || v.y != (T)0 || (pair && (v2.x != (T)0 || v2.y != (T)0));
         if (!nz && !bad1 && !bad2) continue;
       }
-      const bool twin = PAIRED && u < nt;
       int first[3], first2[3] = {0, 0, 0};
       double frac[3], frac2[3] = {0.0, 0.0, 0.0};
       point_taps<sizeof(T) == 4>(g, cur, J, first, frac);
@@ -906,8 +907,8 @@ __device__ __forceinline__ void spread_task(int64_t task_id, const cx<T>* __rest
       if (twin) {
         const cx<T> vs = {v.x + v2.x, v.y + v2.y};
         if (in1)
-          spread_one<T, J, S, SS, false, FIXED>(accp, acc, vs, (l0 * S + l1) * S + l2, w0r, w0i,
-                                                w1r, w1i, w2r, w2i);
+          spread_one<T, J, S, SS, CW, FIXED>(accp, acc, vs, (l0 * S + l1) * S + l2, w0r, w0i,
+                                             w1r, w1i, w2r, w2i);
       } else if constexpr (PAIRED) {
         // (a single point, or a pair whose first cells differ, adds a zero here)
         T x0r[J], x0i[J], x1r[J], x1i[J], x2r[J], x2i[J];

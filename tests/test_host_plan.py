@@ -120,7 +120,8 @@ def check_binning(o, om, pair_spread):
         seg_i = o["perm"][start:start + count]
         assert np.all(key[seg_s] == b)
         assert np.array_equal(np.sort(seg_s), np.sort(seg_i))
-        assert 2 * npairs <= count and (pair_spread or npairs == 0)
+        # (without paired spreading, the only pairs are twins)
+        assert 2 * npairs <= count and (pair_spread or npairs == (ntwins if o["twins"] else 0))
         p = seg_s[:2 * npairs].reshape(-1, 2)
         assert np.array_equal(first[p[:, 0]], first[p[:, 1]])
         # interpolation units: the first ntwins entry pairs sample one
@@ -132,7 +133,7 @@ def check_binning(o, om, pair_spread):
         tw = seg_i[:2 * ntwins].reshape(-1, 2)
         assert np.array_equal(first[tw[:, 0]], first[tw[:, 1]])
         assert np.all(np.abs(om[tw[:, 0]] - om[tw[:, 1]]) <= 1e-12 * np.maximum(1.0, np.abs(om[tw[:, 0]])))
-        if o["twins"] and pair_spread:
+        if o["twins"]:
             assert np.all(same[:ntwins])  # twins first
             assert ntwins == same.sum() and not np.any(same[ntwins:])
             want = {frozenset(q) for q in p[same].tolist()}
