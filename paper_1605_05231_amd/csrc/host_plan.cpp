@@ -67,9 +67,11 @@ void point_omega(const BinParams& p, const std::vector<double>& geom, int64_t i,
 // relative, and one first tap cell) are linked, kept next to each other in
 // the bin and in one task, and paired; their pairs come first in both
 // orders: one evaluation of the weights serves both points in spreading, and
-// one interpolation both outputs.  Tasks and deals otherwise keep the
-// points' own order (cell-sorted tasks and deals measured up to 4x slower in
-// spreading: neighbouring lanes and waves then add to the same cells).
+// one interpolation both outputs.  Tasks are cut from the bins in point
+// order (tasks cut in cell order gathered the coincident omega = 0 samples
+// into one task, whose LDS atomics on that one cell serialised: up to 4x
+// slower spreading); within each residue the spreading deal takes the points
+// in turns over their cells, the interpolation deal in cell order.
 void build_bins(const BinParams& p, const std::vector<double>& geom, Binning& B) {
   const int64_t M = p.M;
   const int nb = p.nb, T = p.tile, J = p.J;
@@ -213,13 +215,15 @@ void build_bins(const BinParams& p, const std::vector<double>& geom, Binning& B)
   B.perm = B.perm_s;
   // Reorder pts[0..n) by residue: classes of residues r = cls, cls + step, ...
   // in turn, each dealt round-robin over its residues.
-  // With `cell` (spreading), each residue's points are first put in turns
-  // over their first cells (one point of every cell, then a second of every
-  // cell that has one, ...), so that the two points a wave takes from one
-  // residue rarely share a cell: lanes adding to the same cell in one LDS
-  // atomic are serialised.
+  // With `cell`, each residue's points are first put in the order of their
+  // first cells; the spreading (step 1) then takes them in turns over the
+  // cells (one point of every cell, then a second of every cell that has
+  // one, ...), so that the two points a wave takes from one residue rarely
+  // share a cell: lanes adding to the same cell in one LDS atomic are
+  // serialised.
   struct Deal {
     std::vector<int32_t> tmp, bucket, cnt = std::vector<int32_t>(33), fill, seg;
+    std::vector<std::pair<int, int>> groups;  // (start, size) of each cell's run
     void run(int32_t* pts, int n, const uint8_t* res, int step, const uint16_t* cell = nullptr) {
       std::fill(cnt.begin(), cnt.end(), 0);
       for (int i = 0; i < n; ++i) cnt[res[pts[i]] + 1]++;
@@ -236,7 +240,7 @@ void build_bins(const BinParams& p, const std::vector<double>& geom, Binning& B)
           std::stable_sort(b, b + m, [&](int32_t x, int32_t y) { return cell[x] < cell[y]; });
           if (step == 2) continue;  // (interpolation: kept in cell order)
           seg.clear();
-          std::vector<std::pair<int, int>> groups;  // (start, size) of each cell's run
+          groups.clear();
           for (int i = 0; i < m;) {
             int j = i;
             while (j < m && cell[b[j]] == cell[b[i]]) ++j;
