@@ -203,7 +203,7 @@ void build_bins(const BinParams& p, const std::vector<double>& geom, Binning& B)
       t.start = (int32_t)q;
       int64_t n = std::min<int64_t>(p.max_pts, e - q);
       // a task never separates twins
-      if (p.twins && q + n < e && twin_of[B.perm_s[q + n - 1]] == B.perm_s[q + n]) --n;
+      if (p.twins && n > 1 && q + n < e && twin_of[B.perm_s[q + n - 1]] == B.perm_s[q + n]) --n;
       t.count = (int32_t)n;
       t.npairs = 0;
       t.ntwins = 0;
