@@ -113,6 +113,11 @@ typedef struct nufftct_grangeat nufftct_grangeat;
  *              n_r samples (enables NUFFTCT_RADIAL; M % n_r == 0, n_r even)
  *   stream     stream for the plan's uploads (NULL = null stream)
  * On success *out receives the plan; on failure *out is NULL.
+ * FP32 plans take two points whose FP64 frequencies agree to 1e-12
+ * (relative) and share their first tap cell as one frequency: one
+ * interpolation gives both outputs, and the adjoint spreads the sum of their
+ * two values with one set of weights (radial lines in opposite directions
+ * sample almost every frequency twice).  FP64 plans treat every point alone.
  */
 int nufftct_plan_create(nufftct_plan** out, int64_t N, int64_t K, int J, int kernel,
                         double beta, int precision, const double* points, int64_t M,
